@@ -1,0 +1,232 @@
+/*
+ * ptebd.h -- C ABI of libptebd, the MI355X (gfx950) pTEBD layer library.
+ *
+ * The library evolves matrix-product states (MPS) in the Vidal form {Gamma, Lambda}
+ * (Sec. II.B, Eq. (mps_cano_decomp)) under layers of non-overlapping two-qubit gates
+ * (Sec. IV, Eq. (circ_decomp)) with the parallel TEBD algorithm of Algorithm 1:
+ * every gate of a layer is applied at once by the TEBD procedure of Sec. II.C, every
+ * updated bond is truncated by the projector compression of Sec. III.B, its Schmidt
+ * values are rescaled by the norm-stabilization factor nu_i = (1 - eps_i)^(-1/2) of
+ * Sec. III.C.2 (Eq. (lren)), and, when the layer had to be compressed, g parallel
+ * trivial-simple-update (PtSU) steps of Sec. III.D follow (IPMC, Sec. III.E).
+ *
+ * Conventions used by every call:
+ *   - Sites q = 0..N-1, bonds i = 0..N.  Lambda[i] sits between sites i-1 and i,
+ *     Lambda[0] = Lambda[N] = (1); it is real, positive, descending and held in FP64.
+ *     Gamma[q] has shape (chi_q, 2, chi_{q+1}) with chi_i = len(Lambda[i]).
+ *   - A gate "at q" acts on sites (q, q+1): it rewrites Lambda[q+1], Gamma[q], Gamma[q+1]
+ *     and reads Lambda[q], Lambda[q+2].
+ *   - A gate is 16 complex128 numbers, interleaved (re, im), row-major 4x4
+ *     U[(s' t'), (s t)] with the left site's index s as the high bit.
+ *   - Host complex arrays are complex128 interleaved (re, im).  Gamma[q] in host
+ *     arrays is C-ordered (a, s, m), i.e. element (a, s, m) at ((a*2 + s)*chi_{q+1} + m).
+ *   - Every call returns an int status: 0 = OK, negative = error, positive = warning.
+ *     After an error the state is unchanged if the error was detected before any
+ *     device work was enqueued (all argument validation happens first).
+ *     ptebd_last_error() returns a thread-local message for the last non-zero status.
+ *   - No C++ exception crosses this interface.
+ *
+ * Ownership: the caller owns every host array it passes; the library copies what it
+ * needs before returning, so the caller may free or reuse them at once.  The library
+ * owns all device memory it allocates; device pointers never leave it.  The handle is
+ * bound to the HIP device current at create time and to the stream given there.
+ * Calls on one handle must not run concurrently from several host threads.
+ */
+#ifndef PTEBD_H
+#define PTEBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define PTEBD_OK 0
+#define PTEBD_EINVAL (-1)        /* bad argument: N, d, chi, cutoff < 0, q out of range, NaN/Inf gate */
+#define PTEBD_EOVERLAP (-2)      /* two gates of one layer share a site of the same state */
+#define PTEBD_ENOMEM (-3)        /* device or pinned host allocation failed */
+#define PTEBD_EDEVICE (-4)       /* a HIP runtime call failed */
+#define PTEBD_ENONFINITE (-5)    /* a non-finite Lambda or singular value was produced */
+#define PTEBD_EANNIHILATED (-6)  /* a two-site wavefunction vanished or eps_i >= 1 */
+#define PTEBD_WNOCONV 1          /* some SVD reached the sweep cap; result usable */
+
+/* ------------------------------------------------------------------ precisions */
+#define PTEBD_FP64 0  /* Gamma, theta and every product in FP64 (FP64 MFMA) */
+#define PTEBD_FP32 1  /* Gamma, theta, Jacobi column updates in FP32 (FP32 MFMA); the
+                         Jacobi rotation angles, singular values, eps, nu, Lambda and
+                         the Lambda^{-1} divisions in FP64 */
+
+/* ------------------------------------------------------------------ layer flags */
+#define PTEBD_FLAG_NO_STABILIZE 1  /* nu_i = 1 (norm-stabilization ablation, Sec. III.C.1) */
+
+typedef struct ptebd_mps* ptebd_mps_t;
+
+/* Per-layer statistics.  The array pointers are caller-owned outputs of length
+ * n_gates (any may be NULL); the scalars are filled by the library. */
+typedef struct {
+  int32_t* k;       /* kept bond dimension of each gate's bond */
+  int32_t* rank;    /* r = #{sigma > cutoff * sigma_1} */
+  double* eps;      /* discarded weight eps_i = sum of the dropped sigma^2 (Theorem 1) */
+  double* nu;       /* stabilization factor applied to Lambda[q+1] */
+  int32_t* sweeps;  /* Jacobi sweeps used by the gate's SVD */
+  int32_t triggered;      /* 1 if some gate had r > chi_max (the layer was compressed) */
+  int32_t ptsu_done;      /* PtSU steps executed after the gates */
+  int32_t max_sweeps;     /* max Jacobi sweeps over all SVDs of the layer, PtSU included */
+  int32_t n_unconverged;  /* SVDs that hit the sweep cap */
+  double device_ms;       /* device time of the layer, from HIP events on the stream */
+} ptebd_layer_stats;
+
+/* Library version string. */
+const char* ptebd_version(void);
+
+/* Thread-local text of the last non-zero status returned on this thread. */
+const char* ptebd_last_error(void);
+
+/*
+ * Create a batch of n_states MPS, each in |0...0> (chi_0 = 1, Sec. IV.A: Gamma[q] = e_0,
+ * every Lambda = (1)).
+ *   n_sites[s]  >= 2, number of qubits of state s;
+ *   chi_cap[s]  in [1, 512], largest bond dimension state s may reach (sizes its device slots:
+ *               N * 2 * chi_cap^2 complex numbers of the chosen precision);
+ *   d           local dimension, must be 2;
+ *   precision   PTEBD_FP64 or PTEBD_FP32;
+ *   hip_stream  hipStream_t every device operation of the handle is ordered on
+ *               (NULL = the null stream); the library does not own it.
+ * Errors: EINVAL, ENOMEM, EDEVICE.  *out is NULL on error.
+ */
+int ptebd_mps_create(int n_states, const int32_t* n_sites, const int32_t* chi_cap, int d,
+                     int precision, void* hip_stream, ptebd_mps_t* out);
+
+/* Free the handle and all its device memory.  NULL is accepted. */
+int ptebd_mps_destroy(ptebd_mps_t h);
+
+/* Set the Jacobi SVD controls of a handle: max_sweeps >= 1 (default 30) and the
+ * relative off-diagonal tolerance factor tol_factor > 0 (a pair of columns counts as
+ * orthogonal when |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit
+ * roundoff of the precision; default 4). */
+int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor);
+
+/*
+ * Apply one circuit layer (one step of Algorithm 1) to states of the batch.
+ *   n_gates      number of gates (>= 0);
+ *   state_idx    [n_gates] state of each gate, or NULL when the handle holds one state;
+ *   bonds        [n_gates] left site q of each gate, 0 <= q <= N-2;
+ *   gates        [n_gates * 32] doubles: 16 complex128 per gate (see conventions);
+ *   chi_max      >= 1 and <= the state's chi_cap: bond-dimension bound chi;
+ *   cutoff       >= 0: singular values sigma <= cutoff * sigma_1 are always dropped
+ *                (their weight counts in eps_i);
+ *   ptsu_steps   g >= 0 PtSU steps run when some gate of the layer had r > chi_max;
+ *   flags        PTEBD_FLAG_NO_STABILIZE or 0;
+ *   stats        optional per-layer statistics (see ptebd_layer_stats).
+ * The gates of one state must act on disjoint sites (else EOVERLAP).  The call enqueues
+ * the layer on the handle's stream and returns after it has completed (the new bond
+ * dimensions are read back to size the next layer).
+ * Errors: EINVAL, EOVERLAP, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV.
+ */
+int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
+                      const int32_t* bonds, const double* gates, int chi_max, double cutoff,
+                      int ptsu_steps, int flags, ptebd_layer_stats* stats);
+
+/* Run g PtSU steps on state s (tSU on all pairs (0,1),(2,3),..., then (1,2),(3,4),...;
+ * each tSU is the TEBD procedure with the identity gate skipped, cutoff only, nu = 1). */
+int ptebd_ptsu(ptebd_mps_t h, int s, int steps, double cutoff);
+
+/* Exact sqrt(<Psi|Psi>) of state s in FP64 by a left-to-right transfer sweep. */
+int ptebd_norm(ptebd_mps_t h, int s, double* out);
+
+/* Exact <Psi_a|Psi_b> in FP64 (states may differ in precision and bond dimensions but
+ * must have the same number of sites). */
+int ptebd_overlap(ptebd_mps_t ha, int sa, ptebd_mps_t hb, int sb, double* re, double* im);
+
+/* <Z_q> / <Psi|Psi> for every site q of state s (out: N doubles), from FP64 left and
+ * right environments. */
+int ptebd_expect_z(ptebd_mps_t h, int s, double* out);
+
+/* Distance to the canonical form, Eq. (dist_to_cano), of state s scaled to norm 1
+ * (every inner Lambda multiplied by n^(-1/(N-1))). */
+int ptebd_canon_distance(ptebd_mps_t h, int s, double* out);
+
+/* n*_upper = prod of every nu_i applied to state s since create/import (Theorem 3). */
+int ptebd_norm_estimate(ptebd_mps_t h, int s, double* out);
+
+/* Fidelity estimate prod over all truncations of (1 - eps_i) since create/import. */
+int ptebd_fidelity_estimate(ptebd_mps_t h, int s, double* out);
+
+/* Bond dimensions chi_0..chi_N of state s into out[0..N] (cap >= N+1). */
+int ptebd_bond_dims(ptebd_mps_t h, int s, int32_t* out, int cap);
+
+/* Lambda[bond] of state s into out (cap doubles); *len receives chi_bond. */
+int ptebd_get_lambda(ptebd_mps_t h, int s, int bond, double* out, int cap, int* len);
+
+/*
+ * Export state s: gamma receives the concatenation over q of Gamma[q] in C order
+ * (a, s, m) as complex128 (gamma_cap counts doubles, >= 2 * sum_q 2 chi_q chi_{q+1});
+ * lambda receives the concatenation of Lambda[0..N] (lambda_cap >= sum_i chi_i).
+ */
+int ptebd_export(ptebd_mps_t h, int s, double* gamma, size_t gamma_cap, double* lambda,
+                 size_t lambda_cap);
+
+/* Import state s from host data in the export format; dims = chi_0..chi_N
+ * (chi_0 = chi_N = 1, every chi_i <= chi_cap).  Resets the nu / eps products to 1. */
+int ptebd_import(ptebd_mps_t h, int s, const int32_t* dims, const double* gamma,
+                 const double* lambda);
+
+/*
+ * Build the two-site wavefunction of a gate at q of state s on the device (the
+ * contraction of Sec. II.C, with the gate applied; gate may be NULL for the identity)
+ * and copy it to out as a complex128 row-major (2 chi_q) x (2 chi_{q+2}) matrix with
+ * rows (a, s') and columns (t', c).  For kernel-level parity checks.
+ */
+int ptebd_debug_theta(ptebd_mps_t h, int s, int q, const double* gate, double* out);
+
+/*
+ * Batched truncated-SVD primitive on the device (the Jacobi SVD used by apply_layer):
+ * for each of `batch` complex128 row-major m x n matrices a[b], compute the singular
+ * values (descending, min(m,n) of them) and the left / right singular vectors:
+ *   s  [batch * kmin] doubles,
+ *   u  [batch * m * kmin * 2] doubles, row-major m x kmin complex (may be NULL),
+ *   vh [batch * kmin * n * 2] doubles, row-major kmin x n complex (may be NULL),
+ * with kmin = min(m, n) <= 1024.  sweeps (optional, [batch]) receives the sweeps used.
+ * precision as in ptebd_mps_create.  Runs on hip_stream and returns when done.
+ */
+int ptebd_svd_batched(int precision, int batch, int m, int n, const double* a, double* s,
+                      double* u, double* vh, int32_t* sweeps, int max_sweeps,
+                      double tol_factor, void* hip_stream);
+
+/* ------------------------------------------------------------------ kernel timing
+ * When profiling is on, every hot-path kernel launch of the handle is bracketed by HIP
+ * events on the handle's stream, and per kernel class the library accumulates the device
+ * time, the number of launches and the algorithmic flops and bytes of those launches:
+ *   THETA      32 chi_q chi_{q+1} chi_{q+2} (+ 128 chi_q chi_{q+2} for the gate mix) flops;
+ *              reads both Gammas, writes theta (complex elements of the precision).
+ *   JACOBI     one block-Jacobi round; per 16+16-column pair: 6144 R flops for the three
+ *              16x16 complex Gram tiles over R rows, plus 8192 (R + C) flops when the pair
+ *              is rotated (32x32 complex update of W's and V's 32 columns); bytes: the 32
+ *              columns of W read once, and those of W and V read and written when rotated.
+ *   FINALIZE   column norms: reads W (R C complex elements); no MFMA flops counted.
+ *   WRITEBACK  reads the k kept columns, writes both Gammas (2 k (chi_q + chi_{q+2})
+ *              complex elements each way).
+ * ptebd_set_profiling(h, 1) enables and resets; ptebd_get_kernel_stats reads a class. */
+#define PTEBD_KERNEL_THETA 0
+#define PTEBD_KERNEL_JACOBI 1
+#define PTEBD_KERNEL_FINALIZE 2
+#define PTEBD_KERNEL_WRITEBACK 3
+#define PTEBD_KERNEL_COUNT 4
+
+typedef struct {
+  double total_ms;   /* summed event-measured duration of the launches */
+  int64_t launches;  /* number of launches */
+  double flops;      /* algorithmic flops of those launches */
+  double bytes;      /* algorithmic HBM bytes of those launches */
+} ptebd_kernel_stats;
+
+int ptebd_set_profiling(ptebd_mps_t h, int enable);
+int ptebd_get_kernel_stats(ptebd_mps_t h, int kind, ptebd_kernel_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTEBD_H */

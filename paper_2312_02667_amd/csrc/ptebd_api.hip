@@ -1,0 +1,1185 @@
+// Host runtime and C ABI of libptebd (see include/ptebd.h).
+//
+// The handle owns a device arena with fixed per-site slots (2 chi_cap^2 complex numbers per
+// Gamma, chi_cap doubles per Lambda), a grow-only layer workspace (work matrices, rotation
+// matrices, descriptors, per-gate outputs) and pinned host staging.  Bond dimensions are
+// mirrored on the host; each layer reads the new dimensions back when it completes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ptebd.h"
+#include "ptebd_internal.h"
+
+using ptebd::cplx;
+using ptebd::GateDesc;
+using ptebd::LayerOut;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define PT_HIP(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(PTEBD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define PT_CHECK(expr)      \
+  do {                      \
+    int st_ = (expr);       \
+    if (st_ < 0) return st_; \
+  } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need) {
+    if (need <= bytes) return PTEBD_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t alloc = std::max<size_t>(need, 256);
+    if (hipMalloc(&p, alloc) != hipSuccess) {
+      p = nullptr;
+      return fail(PTEBD_ENOMEM, "device allocation of " + std::to_string(alloc) + " bytes failed");
+    }
+    bytes = alloc;
+    return PTEBD_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// Grow-only pinned host buffer.
+struct HostBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need) {
+    if (need <= bytes) return PTEBD_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    size_t alloc = std::max<size_t>(need, 256);
+    if (hipHostMalloc(&p, alloc, hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return fail(PTEBD_ENOMEM, "pinned host allocation failed");
+    }
+    bytes = alloc;
+    return PTEBD_OK;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+struct StateInfo {
+  int n = 0;
+  int cap = 0;
+  std::vector<int32_t> dims;  // chi_0..chi_N
+  size_t gamma_off = 0;       // complex elements
+  size_t lam_off = 0;         // doubles
+  double prod_nu = 1.0;
+  double prod_fid = 1.0;
+};
+
+// One bond update: gate (host pointer to 32 doubles) at q of state s, or the identity.
+struct Item {
+  int s;
+  int q;
+  const double* gate;
+};
+
+struct UpdateResult {
+  std::vector<int32_t> k, r, sweeps;
+  std::vector<double> eps, nu;
+  int max_sweeps = 0;
+  int n_unconverged = 0;
+};
+
+// Event-based per-kernel timing (enabled by ptebd_set_profiling).
+struct Prof {
+  bool on = false;
+  struct Pend {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pend> pending;
+  ptebd_kernel_stats st[PTEBD_KERNEL_COUNT];
+  Prof() { reset(); }
+  void reset() {
+    for (auto& x : st) x = ptebd_kernel_stats{0.0, 0, 0.0, 0.0};
+  }
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // Harvest finished launches (the stream has been synchronized).
+  void harvest() {
+    for (const Pend& p : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        st[p.kind].total_ms += ms;
+        st[p.kind].launches += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void release() {
+    harvest();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
+// Launch `fn` on `stream`, bracketed by events when profiling is on.
+template <class F>
+void timed(Prof* pf, int kind, hipStream_t stream, F fn) {
+  if (!pf || !pf->on) {
+    fn();
+    return;
+  }
+  hipEvent_t a = pf->get(), b = pf->get();
+  if (!a || !b) {
+    fn();
+    return;
+  }
+  (void)hipEventRecord(a, stream);
+  fn();
+  (void)hipEventRecord(b, stream);
+  pf->pending.push_back({kind, a, b});
+}
+
+double unit_roundoff(int precision) {
+  return precision == PTEBD_FP64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+}
+
+}  // namespace
+
+struct ptebd_mps {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int precision = PTEBD_FP64;
+  size_t celem = 16;  // bytes per complex element
+  std::vector<StateInfo> st;
+  DevBuf gamma, lam;
+  DevBuf work, desc, gates, outbuf, qscratch, renv, qout;
+  HostBuf h_desc, h_gates, h_out, h_small;
+  Prof prof;
+  int max_sweeps = 30;
+  double tol_factor = 4.0;
+  int inner_sweeps = 2;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  char* gamma_slot(int s, int q) const {
+    const StateInfo& si = st[s];
+    return (char*)gamma.p + (si.gamma_off + (size_t)q * 2 * si.cap * si.cap) * celem;
+  }
+  double* lam_slot(int s, int i) const {
+    const StateInfo& si = st[s];
+    return (double*)lam.p + si.lam_off + (size_t)i * si.cap;
+  }
+};
+
+namespace {
+
+// Layout of the per-gate output block inside outbuf.
+struct OutLayout {
+  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, work, total;
+};
+
+OutLayout out_layout(int n, int cmax) {
+  OutLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  L.sig = take(sizeof(double) * (size_t)n * cmax);
+  L.perm = take(sizeof(int32_t) * (size_t)n * cmax);
+  L.k = take(sizeof(int32_t) * n);
+  L.r = take(sizeof(int32_t) * n);
+  L.eps = take(sizeof(double) * n);
+  L.nu = take(sizeof(double) * n);
+  L.sweeps = take(sizeof(int32_t) * n);
+  L.conv = take(sizeof(int32_t) * n);
+  L.offbits = take(sizeof(uint32_t) * n);
+  L.counters = take(sizeof(int32_t) * 4);
+  L.work = take(sizeof(unsigned long long) * 4);
+  L.total = off;
+  return L;
+}
+
+LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
+  char* b = (char*)base;
+  LayerOut o;
+  o.sig = (double*)(b + L.sig);
+  o.perm = (int32_t*)(b + L.perm);
+  o.k = (int32_t*)(b + L.k);
+  o.r = (int32_t*)(b + L.r);
+  o.eps = (double*)(b + L.eps);
+  o.nu = (double*)(b + L.nu);
+  o.sweeps = (int32_t*)(b + L.sweeps);
+  o.conv = (int32_t*)(b + L.conv);
+  o.offbits = (uint32_t*)(b + L.offbits);
+  o.counters = (int32_t*)(b + L.counters);
+  o.work = (unsigned long long*)(b + L.work);
+  o.cmax = cmax;
+  return o;
+}
+
+// Sweeps of the block Jacobi SVD on descriptors already on the device.
+template <class T>
+int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, const LayerOut& lo,
+               int precision, int max_sweeps, double tol_factor, int inner_sweeps,
+               int32_t* h_counter, int* n_unconverged, Prof* pf) {
+  ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
+  int nb = (max_c + 15) / 16;
+  int nbp = nb + (nb & 1);
+  if (nbp < 2) nbp = 2;
+  const double u = unit_roundoff(precision);
+  int remaining = n;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int round = 0; round < nbp - 1; ++round)
+      timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
+        ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
+                                      stream);
+      });
+    ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
+    PT_HIP(hipGetLastError());
+    PT_HIP(hipMemcpyAsync(h_counter, lo.counters + (sweep & 1), sizeof(int32_t),
+                          hipMemcpyDeviceToHost, stream));
+    PT_HIP(hipStreamSynchronize(stream));
+    if (pf) pf->harvest();
+    remaining = *h_counter;
+    if (remaining == 0) break;
+  }
+  *n_unconverged = remaining;
+  return PTEBD_OK;
+}
+
+// One batch of independent bond updates (all gates of a layer, or one PtSU half-step).
+template <class T>
+int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, double cutoff,
+                int stabilize, UpdateResult* res) {
+  const int n = (int)items.size();
+  res->k.assign(n, 0);
+  res->r.assign(n, 0);
+  res->sweeps.assign(n, 0);
+  res->eps.assign(n, 0.0);
+  res->nu.assign(n, 1.0);
+  res->max_sweeps = 0;
+  res->n_unconverged = 0;
+  if (n == 0) return PTEBD_OK;
+  if (n > 65535) return fail(PTEBD_EINVAL, "too many bond updates in one batch (max 65535)");
+
+  std::vector<size_t> woff(n), voff(n);
+  size_t total = 0;
+  int max_c = 1, max_tiles = 1, cmax = 1;
+  std::vector<GateDesc> descs(n);
+  for (int i = 0; i < n; ++i) {
+    const StateInfo& si = h->st[items[i].s];
+    const int q = items[i].q;
+    GateDesc& d = descs[i];
+    std::memset(&d, 0, sizeof(d));
+    d.cl = si.dims[q];
+    d.cm = si.dims[q + 1];
+    d.cr = si.dims[q + 2];
+    const int m = 2 * d.cl, nn = 2 * d.cr;
+    d.transposed = nn > m ? 1 : 0;
+    d.R = std::max(m, nn);
+    d.C = std::min(m, nn);
+    d.has_gate = items[i].gate != nullptr ? 1 : 0;
+    // tSU (chi_max <= 0): theta = A B has rank <= chi_{q+1}, so the kept dimension is
+    // bounded by it; singular values beyond it are rounding noise of the precision.
+    d.chi_max = chi_max > 0 ? chi_max : d.cm;
+    d.stabilize = stabilize;
+    woff[i] = total;
+    total += (size_t)d.R * d.C;
+    voff[i] = total;
+    total += (size_t)d.C * d.C;
+    max_c = std::max(max_c, d.C);
+    cmax = std::max(cmax, d.C);
+    max_tiles = std::max(max_tiles, ((d.cl + 31) / 32) * ((d.cr + 31) / 32));
+  }
+  const OutLayout L = out_layout(n, cmax);
+  PT_CHECK(h->work.ensure(total * sizeof(cplx<T>)));
+  PT_CHECK(h->desc.ensure(sizeof(GateDesc) * n));
+  PT_CHECK(h->gates.ensure(sizeof(double) * 32 * n));
+  PT_CHECK(h->outbuf.ensure(L.total));
+  PT_CHECK(h->h_desc.ensure(sizeof(GateDesc) * n));
+  PT_CHECK(h->h_gates.ensure(sizeof(double) * 32 * n));
+  PT_CHECK(h->h_out.ensure(L.total));
+  PT_CHECK(h->h_small.ensure(64));
+
+  char* wbase = (char*)h->work.p;
+  double* hg = (double*)h->h_gates.p;
+  for (int i = 0; i < n; ++i) {
+    GateDesc& d = descs[i];
+    const int s = items[i].s, q = items[i].q;
+    d.gq = h->gamma_slot(s, q);
+    d.gq1 = h->gamma_slot(s, q + 1);
+    d.lam_l = h->lam_slot(s, q);
+    d.lam_m = h->lam_slot(s, q + 1);
+    d.lam_r = h->lam_slot(s, q + 2);
+    d.w = wbase + woff[i] * sizeof(cplx<T>);
+    d.v = wbase + voff[i] * sizeof(cplx<T>);
+    if (items[i].gate) {
+      std::memcpy(hg + 32 * i, items[i].gate, 32 * sizeof(double));
+      d.gate = (const double*)h->gates.p + 32 * i;
+    } else {
+      d.gate = nullptr;
+    }
+  }
+  std::memcpy(h->h_desc.p, descs.data(), sizeof(GateDesc) * n);
+  hipStream_t stream = h->stream;
+  PT_HIP(hipMemcpyAsync(h->desc.p, h->h_desc.p, sizeof(GateDesc) * n, hipMemcpyHostToDevice,
+                        stream));
+  PT_HIP(hipMemcpyAsync(h->gates.p, h->h_gates.p, sizeof(double) * 32 * n, hipMemcpyHostToDevice,
+                        stream));
+  const GateDesc* d_desc = (const GateDesc*)h->desc.p;
+  const LayerOut lo = make_layer_out(h->outbuf.p, L, cmax);
+
+  Prof* pf = &h->prof;
+  timed(pf, PTEBD_KERNEL_THETA, stream, [&] { ptebd::launch_theta<T>(d_desc, n, max_tiles, stream); });
+  PT_HIP(hipGetLastError());
+  int n_unconv = 0;
+  PT_CHECK(run_jacobi<T>(stream, d_desc, n, max_c, lo, h->precision, h->max_sweeps,
+                         h->tol_factor, h->inner_sweeps, (int32_t*)h->h_small.p, &n_unconv, pf));
+  timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_desc, n, cutoff, lo, stream); });
+  timed(pf, PTEBD_KERNEL_WRITEBACK, stream, [&] { ptebd::launch_writeback<T>(d_desc, n, lo, stream); });
+  PT_HIP(hipGetLastError());
+  // copy back the small per-gate outputs (k .. counters are contiguous after perm)
+  PT_HIP(hipMemcpyAsync((char*)h->h_out.p + L.k, (char*)h->outbuf.p + L.k, L.total - L.k,
+                        hipMemcpyDeviceToHost, stream));
+  PT_HIP(hipStreamSynchronize(stream));
+  const char* ho = (const char*)h->h_out.p;
+  const int32_t* hk = (const int32_t*)(ho + L.k);
+  const int32_t* hr = (const int32_t*)(ho + L.r);
+  const double* he = (const double*)(ho + L.eps);
+  const double* hn = (const double*)(ho + L.nu);
+  const int32_t* hs = (const int32_t*)(ho + L.sweeps);
+  const int32_t* hc = (const int32_t*)(ho + L.counters);
+  for (int i = 0; i < n; ++i) {
+    res->k[i] = hk[i];
+    res->r[i] = hr[i];
+    res->eps[i] = he[i];
+    res->nu[i] = hn[i];
+    res->sweeps[i] = hs[i];
+    res->max_sweeps = std::max(res->max_sweeps, hs[i]);
+    h->st[items[i].s].dims[items[i].q + 1] = hk[i];
+  }
+  res->n_unconverged = n_unconv;
+  if (pf->on) {
+    pf->harvest();
+    const double ce = (double)sizeof(cplx<T>);
+    const unsigned long long* hw = (const unsigned long long*)(ho + L.work);
+    pf->st[PTEBD_KERNEL_JACOBI].flops += 6144.0 * (double)hw[0] + 8192.0 * (double)hw[1];
+    pf->st[PTEBD_KERNEL_JACOBI].bytes += ce * (32.0 * (double)hw[0] + 64.0 * (double)hw[1]);
+    for (int i = 0; i < n; ++i) {
+      const GateDesc& d = descs[i];
+      const double cl = d.cl, cm = d.cm, cr = d.cr, kk = hk[i];
+      pf->st[PTEBD_KERNEL_THETA].flops += 32.0 * cl * cm * cr + (d.has_gate ? 128.0 * cl * cr : 0.0);
+      pf->st[PTEBD_KERNEL_THETA].bytes += ce * (2.0 * cl * cm + 2.0 * cm * cr + 4.0 * cl * cr);
+      pf->st[PTEBD_KERNEL_FINALIZE].bytes += ce * (double)d.R * d.C;
+      pf->st[PTEBD_KERNEL_WRITEBACK].bytes += ce * 4.0 * kk * (cl + cr);
+    }
+  }
+  if (hc[2] & 1) return fail(PTEBD_EANNIHILATED, "a two-site wavefunction vanished or eps >= 1");
+  if (hc[2] & 2) return fail(PTEBD_ENONFINITE, "non-finite singular value, eps or nu produced");
+  return PTEBD_OK;
+}
+
+int run_updates_dispatch(ptebd_mps* h, const std::vector<Item>& items, int chi_max,
+                         double cutoff, int stabilize, UpdateResult* res) {
+  if (h->precision == PTEBD_FP64) return run_updates<double>(h, items, chi_max, cutoff, stabilize, res);
+  return run_updates<float>(h, items, chi_max, cutoff, stabilize, res);
+}
+
+int check_handle(ptebd_mps* h) {
+  if (!h) return fail(PTEBD_EINVAL, "null handle");
+  return PTEBD_OK;
+}
+
+int check_state(ptebd_mps* h, int s) {
+  PT_CHECK(check_handle(h));
+  if (s < 0 || s >= (int)h->st.size()) return fail(PTEBD_EINVAL, "state index out of range");
+  return PTEBD_OK;
+}
+
+int set_device(ptebd_mps* h) {
+  PT_HIP(hipSetDevice(h->device));
+  return PTEBD_OK;
+}
+
+// Run `steps` PtSU steps on the listed states (each a tSU on all even-q pairs, then all odd).
+int run_ptsu(ptebd_mps* h, const std::vector<int>& states, int steps, double cutoff,
+             int* max_sweeps, int* n_unconv) {
+  for (int step = 0; step < steps; ++step) {
+    for (int parity = 0; parity < 2; ++parity) {
+      std::vector<Item> items;
+      for (int s : states)
+        for (int q = parity; q + 1 < h->st[s].n; q += 2) items.push_back({s, q, nullptr});
+      UpdateResult res;
+      PT_CHECK(run_updates_dispatch(h, items, 0, cutoff, 0, &res));
+      *max_sweeps = std::max(*max_sweeps, res.max_sweeps);
+      *n_unconv += res.n_unconverged;
+    }
+  }
+  return PTEBD_OK;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------- queries
+size_t qscratch_elems(int cap) { return (size_t)cap * cap; }
+
+// Scratch blocks (each cap x cap complex double): E, E2, A0/A1 (2), B0/B1 (2), F0/F1 (2).
+struct QScratch {
+  cplx<double>* e;
+  cplx<double>* e2;
+  cplx<double>* a;  // two planes
+  cplx<double>* b;  // two planes
+  cplx<double>* f;  // two planes
+  double* red;      // reduction outputs
+};
+
+int get_qscratch(ptebd_mps* h, int cap, QScratch* q, size_t n_red) {
+  const size_t blk = qscratch_elems(cap) * sizeof(cplx<double>);
+  PT_CHECK(h->qscratch.ensure(blk * 8 + sizeof(double) * n_red + 256));
+  char* b = (char*)h->qscratch.p;
+  q->e = (cplx<double>*)(b);
+  q->e2 = (cplx<double>*)(b + blk);
+  q->a = (cplx<double>*)(b + 2 * blk);
+  q->b = (cplx<double>*)(b + 4 * blk);
+  q->f = (cplx<double>*)(b + 6 * blk);
+  q->red = (double*)(b + 8 * blk);
+  return PTEBD_OK;
+}
+
+void site_a(const ptebd_mps* h, int s, int q, const double* lam_left, const double* lam_right,
+            double sl, double sr, cplx<double>* out) {
+  const StateInfo& si = h->st[s];
+  const int cl = si.dims[q], cm = si.dims[q + 1];
+  if (h->precision == PTEBD_FP64)
+    ptebd::launch_site_a<double>(h->gamma_slot(s, q), lam_left, lam_right, cl, cm, sl, sr, out,
+                                 h->stream);
+  else
+    ptebd::launch_site_a<float>(h->gamma_slot(s, q), lam_left, lam_right, cl, cm, sl, sr, out,
+                                h->stream);
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char* ptebd_version(void) { return "ptebd 0.1.0 (gfx950)"; }
+
+const char* ptebd_last_error(void) { return g_last_error.c_str(); }
+
+int ptebd_mps_create(int n_states, const int32_t* n_sites, const int32_t* chi_cap, int d,
+                     int precision, void* hip_stream, ptebd_mps_t* out) {
+  if (!out) return fail(PTEBD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_states < 1 || !n_sites || !chi_cap) return fail(PTEBD_EINVAL, "need n_states >= 1 and arrays");
+  if (d != 2) return fail(PTEBD_EINVAL, "local dimension d must be 2");
+  if (precision != PTEBD_FP64 && precision != PTEBD_FP32)
+    return fail(PTEBD_EINVAL, "precision must be PTEBD_FP64 or PTEBD_FP32");
+  for (int s = 0; s < n_states; ++s) {
+    if (n_sites[s] < 2) return fail(PTEBD_EINVAL, "every state needs n_sites >= 2");
+    if (chi_cap[s] < 1 || chi_cap[s] > 512) return fail(PTEBD_EINVAL, "chi_cap must be in [1, 512]");
+  }
+  ptebd_mps* h = new (std::nothrow) ptebd_mps();
+  if (!h) return fail(PTEBD_ENOMEM, "host allocation failed");
+  auto cleanup = [&](int code) {
+    ptebd_mps_destroy(h);
+    return code;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return cleanup(fail(PTEBD_EDEVICE, "no HIP device"));
+  h->stream = (hipStream_t)hip_stream;
+  h->precision = precision;
+  h->celem = precision == PTEBD_FP64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
+  size_t goff = 0, loff = 0;
+  h->st.resize(n_states);
+  int total_sites = 0, total_bonds = 0;
+  for (int s = 0; s < n_states; ++s) {
+    StateInfo& si = h->st[s];
+    si.n = n_sites[s];
+    si.cap = chi_cap[s];
+    si.dims.assign(si.n + 1, 1);
+    si.gamma_off = goff;
+    si.lam_off = loff;
+    goff += (size_t)si.n * 2 * si.cap * si.cap;
+    loff += (size_t)(si.n + 1) * si.cap;
+    total_sites += si.n;
+    total_bonds += si.n + 1;
+  }
+  int st = h->gamma.ensure(goff * h->celem);
+  if (st < 0) return cleanup(st);
+  st = h->lam.ensure(loff * sizeof(double));
+  if (st < 0) return cleanup(st);
+  if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess)
+    return cleanup(fail(PTEBD_EDEVICE, "hipEventCreate failed"));
+  std::vector<size_t> go, lo;
+  for (int s = 0; s < n_states; ++s) {
+    const StateInfo& si = h->st[s];
+    for (int q = 0; q < si.n; ++q) go.push_back((si.gamma_off + (size_t)q * 2 * si.cap * si.cap) * h->celem);
+    for (int i = 0; i <= si.n; ++i) lo.push_back(si.lam_off + (size_t)i * si.cap);
+  }
+  DevBuf offs;
+  st = offs.ensure(sizeof(size_t) * (go.size() + lo.size()));
+  if (st < 0) return cleanup(st);
+  size_t* d_go = (size_t*)offs.p;
+  size_t* d_lo = d_go + go.size();
+  if (hipMemcpyAsync(d_go, go.data(), sizeof(size_t) * go.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+      hipMemcpyAsync(d_lo, lo.data(), sizeof(size_t) * lo.size(), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return cleanup(fail(PTEBD_EDEVICE, "copy of slot offsets failed"));
+  if (precision == PTEBD_FP64)
+    ptebd::launch_init_product<double>(h->gamma.p, d_go, total_sites, (double*)h->lam.p, d_lo,
+                                       total_bonds, h->stream);
+  else
+    ptebd::launch_init_product<float>(h->gamma.p, d_go, total_sites, (double*)h->lam.p, d_lo,
+                                      total_bonds, h->stream);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) {
+    offs.release();
+    return cleanup(fail(PTEBD_EDEVICE, "initialization of |0...0> failed"));
+  }
+  offs.release();
+  *out = h;
+  return PTEBD_OK;
+}
+
+int ptebd_mps_destroy(ptebd_mps_t h) {
+  if (!h) return PTEBD_OK;
+  if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+  h->gamma.release();
+  h->lam.release();
+  h->work.release();
+  h->desc.release();
+  h->gates.release();
+  h->outbuf.release();
+  h->qscratch.release();
+  h->renv.release();
+  h->qout.release();
+  h->h_desc.release();
+  h->h_gates.release();
+  h->h_out.release();
+  h->h_small.release();
+  h->prof.release();
+  if (h->ev0) (void)hipEventDestroy(h->ev0);
+  if (h->ev1) (void)hipEventDestroy(h->ev1);
+  delete h;
+  return PTEBD_OK;
+}
+
+int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor) {
+  PT_CHECK(check_handle(h));
+  if (max_sweeps < 1 || !(tol_factor > 0.0) || !std::isfinite(tol_factor))
+    return fail(PTEBD_EINVAL, "need max_sweeps >= 1 and tol_factor > 0");
+  h->max_sweeps = max_sweeps;
+  h->tol_factor = tol_factor;
+  return PTEBD_OK;
+}
+
+int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
+                      const int32_t* bonds, const double* gates, int chi_max, double cutoff,
+                      int ptsu_steps, int flags, ptebd_layer_stats* stats) {
+  PT_CHECK(check_handle(h));
+  if (n_gates < 0) return fail(PTEBD_EINVAL, "n_gates < 0");
+  if (n_gates > 0 && (!bonds || !gates)) return fail(PTEBD_EINVAL, "bonds / gates are NULL");
+  if (!state_idx && h->st.size() != 1 && n_gates > 0)
+    return fail(PTEBD_EINVAL, "state_idx may be NULL only for a single-state handle");
+  if (!(cutoff >= 0.0) || !(cutoff < 1.0)) return fail(PTEBD_EINVAL, "cutoff must be in [0, 1)");
+  if (ptsu_steps < 0) return fail(PTEBD_EINVAL, "ptsu_steps < 0");
+  if (flags & ~PTEBD_FLAG_NO_STABILIZE) return fail(PTEBD_EINVAL, "unknown flags");
+  if (chi_max < 1) return fail(PTEBD_EINVAL, "chi_max must be >= 1");
+  std::vector<std::vector<char>> used(h->st.size());
+  std::vector<Item> items(n_gates);
+  for (int i = 0; i < n_gates; ++i) {
+    const int s = state_idx ? state_idx[i] : 0;
+    if (s < 0 || s >= (int)h->st.size()) return fail(PTEBD_EINVAL, "state index out of range");
+    const StateInfo& si = h->st[s];
+    if (chi_max > si.cap) return fail(PTEBD_EINVAL, "chi_max exceeds the state's chi_cap");
+    const int q = bonds[i];
+    if (q < 0 || q + 1 >= si.n) return fail(PTEBD_EINVAL, "bond q out of range");
+    if (used[s].empty()) used[s].assign(si.n, 0);
+    if (used[s][q] || used[s][q + 1])
+      return fail(PTEBD_EOVERLAP, "gates overlap at site " + std::to_string(q) + " of state " + std::to_string(s));
+    used[s][q] = used[s][q + 1] = 1;
+    if (!finite_all(gates + 32 * (size_t)i, 32)) return fail(PTEBD_EINVAL, "non-finite gate entry");
+    // the new bond must fit the slot: min(2 chi_q, 2 chi_{q+2}) is capped by chi_max
+    items[i] = {s, q, gates + 32 * (size_t)i};
+  }
+  PT_CHECK(set_device(h));
+  PT_HIP(hipEventRecord(h->ev0, h->stream));
+  UpdateResult res;
+  PT_CHECK(run_updates_dispatch(h, items, chi_max, cutoff, (flags & PTEBD_FLAG_NO_STABILIZE) ? 0 : 1, &res));
+  std::vector<int> trig_states;
+  std::vector<char> trig(h->st.size(), 0);
+  for (int i = 0; i < n_gates; ++i)
+    if (res.r[i] > chi_max) trig[items[i].s] = 1;
+  for (size_t s = 0; s < trig.size(); ++s)
+    if (trig[s]) trig_states.push_back((int)s);
+  for (int i = 0; i < n_gates; ++i) {
+    StateInfo& si = h->st[items[i].s];
+    si.prod_nu *= res.nu[i];
+    si.prod_fid *= (1.0 - res.eps[i]);
+  }
+  int max_sw = res.max_sweeps, n_unconv = res.n_unconverged, ptsu_done = 0;
+  if (ptsu_steps > 0 && !trig_states.empty()) {
+    PT_CHECK(run_ptsu(h, trig_states, ptsu_steps, cutoff, &max_sw, &n_unconv));
+    ptsu_done = ptsu_steps;
+  }
+  PT_HIP(hipEventRecord(h->ev1, h->stream));
+  PT_HIP(hipEventSynchronize(h->ev1));
+  float ms = 0.f;
+  PT_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  if (stats) {
+    for (int i = 0; i < n_gates; ++i) {
+      if (stats->k) stats->k[i] = res.k[i];
+      if (stats->rank) stats->rank[i] = res.r[i];
+      if (stats->eps) stats->eps[i] = res.eps[i];
+      if (stats->nu) stats->nu[i] = res.nu[i];
+      if (stats->sweeps) stats->sweeps[i] = res.sweeps[i];
+    }
+    stats->triggered = trig_states.empty() ? 0 : 1;
+    stats->ptsu_done = ptsu_done;
+    stats->max_sweeps = max_sw;
+    stats->n_unconverged = n_unconv;
+    stats->device_ms = ms;
+  }
+  if (n_unconv > 0) return fail(PTEBD_WNOCONV, "some SVDs reached the sweep cap");
+  return PTEBD_OK;
+}
+
+int ptebd_set_profiling(ptebd_mps_t h, int enable) {
+  PT_CHECK(check_handle(h));
+  PT_HIP(hipStreamSynchronize(h->stream));
+  h->prof.harvest();
+  h->prof.reset();
+  h->prof.on = enable != 0;
+  return PTEBD_OK;
+}
+
+int ptebd_get_kernel_stats(ptebd_mps_t h, int kind, ptebd_kernel_stats* out) {
+  PT_CHECK(check_handle(h));
+  if (kind < 0 || kind >= PTEBD_KERNEL_COUNT || !out) return fail(PTEBD_EINVAL, "bad kernel class");
+  PT_HIP(hipStreamSynchronize(h->stream));
+  h->prof.harvest();
+  *out = h->prof.st[kind];
+  return PTEBD_OK;
+}
+
+int ptebd_ptsu(ptebd_mps_t h, int s, int steps, double cutoff) {
+  PT_CHECK(check_state(h, s));
+  if (steps < 0) return fail(PTEBD_EINVAL, "steps < 0");
+  if (!(cutoff >= 0.0) || !(cutoff < 1.0)) return fail(PTEBD_EINVAL, "cutoff must be in [0, 1)");
+  PT_CHECK(set_device(h));
+  int ms = 0, nu = 0;
+  PT_CHECK(run_ptsu(h, std::vector<int>{s}, steps, cutoff, &ms, &nu));
+  if (nu > 0) return fail(PTEBD_WNOCONV, "some SVDs reached the sweep cap");
+  return PTEBD_OK;
+}
+
+int ptebd_overlap(ptebd_mps_t ha, int sa, ptebd_mps_t hb, int sb, double* re, double* im) {
+  PT_CHECK(check_state(ha, sa));
+  PT_CHECK(check_state(hb, sb));
+  if (!re || !im) return fail(PTEBD_EINVAL, "null output");
+  const StateInfo& A = ha->st[sa];
+  const StateInfo& B = hb->st[sb];
+  if (A.n != B.n) return fail(PTEBD_EINVAL, "states differ in the number of sites");
+  if (ha->device != hb->device) return fail(PTEBD_EINVAL, "handles live on different devices");
+  PT_CHECK(set_device(ha));
+  // order hb's work after its pending work, then run everything on ha's stream
+  PT_HIP(hipStreamSynchronize(hb->stream));
+  const int cap = std::max(A.cap, B.cap);
+  QScratch q;
+  PT_CHECK(get_qscratch(ha, cap, &q, 4));
+  hipStream_t stream = ha->stream;
+  ptebd::launch_set_identity_scalar(q.e, 1.0, stream);
+  const size_t blk = qscratch_elems(cap);
+  for (int site = 0; site < A.n; ++site) {
+    const int cla = A.dims[site], cma = A.dims[site + 1];
+    const int clb = B.dims[site], cmb = B.dims[site + 1];
+    site_a(ha, sa, site, ha->lam_slot(sa, site), nullptr, 1.0, 1.0, q.a);
+    site_a(hb, sb, site, hb->lam_slot(sb, site), nullptr, 1.0, 1.0, q.b);
+    // F_s = E B_s : (cla x clb)(clb x cmb)
+    for (int s = 0; s < 2; ++s)
+      ptebd::launch_zgemm('N', 'N', cla, cmb, clb, 1.0, q.e, cla, q.b + (size_t)s * clb * cmb, clb,
+                          0.0, q.f + s * blk, cla, stream);
+    // E' = sum_s A_s^H F_s : (cma x cla)(cla x cmb)
+    for (int s = 0; s < 2; ++s)
+      ptebd::launch_zgemm('C', 'N', cma, cmb, cla, 1.0, q.a + (size_t)s * cla * cma, cla,
+                          q.f + s * blk, cla, s == 0 ? 0.0 : 1.0, q.e2, cma, stream);
+    std::swap(q.e, q.e2);
+  }
+  PT_HIP(hipGetLastError());
+  cplx<double> hv;
+  PT_HIP(hipMemcpyAsync(&hv, q.e, sizeof(hv), hipMemcpyDeviceToHost, stream));
+  PT_HIP(hipStreamSynchronize(stream));
+  // Lambda[N] = (1) for both states
+  *re = hv.re;
+  *im = hv.im;
+  return PTEBD_OK;
+}
+
+int ptebd_norm(ptebd_mps_t h, int s, double* out) {
+  if (!out) return fail(PTEBD_EINVAL, "null output");
+  double re = 0, im = 0;
+  PT_CHECK(ptebd_overlap(h, s, h, s, &re, &im));
+  *out = std::sqrt(std::max(re, 0.0));
+  return PTEBD_OK;
+}
+
+int ptebd_expect_z(ptebd_mps_t h, int s, double* out) {
+  PT_CHECK(check_state(h, s));
+  if (!out) return fail(PTEBD_EINVAL, "null output");
+  PT_CHECK(set_device(h));
+  const StateInfo& si = h->st[s];
+  const int n = si.n, cap = si.cap;
+  const size_t blk = qscratch_elems(cap);
+  QScratch q;
+  PT_CHECK(get_qscratch(h, cap, &q, (size_t)n + 4));
+  PT_CHECK(h->renv.ensure(sizeof(cplx<double>) * blk * (size_t)(n + 1)));
+  cplx<double>* renv = (cplx<double>*)h->renv.p;
+  hipStream_t stream = h->stream;
+  PT_HIP(hipMemsetAsync(q.red, 0, sizeof(double) * (n + 4), stream));
+  // right environments R[q] = sum_s A_s R[q+1] A_s^H, R[N] = (1)
+  ptebd::launch_set_identity_scalar(renv + (size_t)n * blk, 1.0, stream);
+  for (int site = n - 1; site >= 0; --site) {
+    const int cl = si.dims[site], cm = si.dims[site + 1];
+    site_a(h, s, site, h->lam_slot(s, site), nullptr, 1.0, 1.0, q.a);
+    for (int p = 0; p < 2; ++p)
+      ptebd::launch_zgemm('N', 'N', cl, cm, cm, 1.0, q.a + (size_t)p * cl * cm, cl,
+                          renv + (size_t)(site + 1) * blk, cm, 0.0, q.f + p * blk, cl, stream);
+    for (int p = 0; p < 2; ++p)
+      ptebd::launch_zgemm('N', 'C', cl, cl, cm, 1.0, q.f + p * blk, cl, q.a + (size_t)p * cl * cm,
+                          cl, p == 0 ? 0.0 : 1.0, renv + (size_t)site * blk, cl, stream);
+  }
+  // left sweep with <Z_q> on the fly: z_q = sum_s z_s Tr(A_s^H L A_s R[q+1])
+  ptebd::launch_set_identity_scalar(q.e, 1.0, stream);
+  for (int site = 0; site < n; ++site) {
+    const int cl = si.dims[site], cm = si.dims[site + 1];
+    site_a(h, s, site, h->lam_slot(s, site), nullptr, 1.0, 1.0, q.a);
+    for (int p = 0; p < 2; ++p) {
+      // F_p = L A_p (cl x cm)
+      ptebd::launch_zgemm('N', 'N', cl, cm, cl, 1.0, q.e, cl, q.a + (size_t)p * cl * cm, cl, 0.0,
+                          q.f + p * blk, cl, stream);
+      // B_p = F_p R[q+1] (cl x cm), stored in q.b planes
+      ptebd::launch_zgemm('N', 'N', cl, cm, cm, 1.0, q.f + p * blk, cl,
+                          renv + (size_t)(site + 1) * blk, cm, 0.0, q.b + p * blk, cl, stream);
+      ptebd::launch_dot_conj(q.a + (size_t)p * cl * cm, q.b + p * blk, cl * cm, p == 0 ? 1.0 : -1.0,
+                             q.red + site, stream);
+    }
+    // L' = sum_p A_p^H F_p (cm x cm)
+    for (int p = 0; p < 2; ++p)
+      ptebd::launch_zgemm('C', 'N', cm, cm, cl, 1.0, q.a + (size_t)p * cl * cm, cl, q.f + p * blk,
+                          cl, p == 0 ? 0.0 : 1.0, q.e2, cm, stream);
+    std::swap(q.e, q.e2);
+  }
+  PT_HIP(hipGetLastError());
+  std::vector<double> z(n);
+  cplx<double> nrm;
+  PT_HIP(hipMemcpyAsync(z.data(), q.red, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+  PT_HIP(hipMemcpyAsync(&nrm, q.e, sizeof(nrm), hipMemcpyDeviceToHost, stream));
+  PT_HIP(hipStreamSynchronize(stream));
+  for (int i = 0; i < n; ++i) out[i] = z[i] / nrm.re;
+  return PTEBD_OK;
+}
+
+int ptebd_canon_distance(ptebd_mps_t h, int s, double* out) {
+  PT_CHECK(check_state(h, s));
+  if (!out) return fail(PTEBD_EINVAL, "null output");
+  double nrm = 0;
+  PT_CHECK(ptebd_norm(h, s, &nrm));
+  if (!(nrm > 0)) return fail(PTEBD_EANNIHILATED, "zero norm");
+  const StateInfo& si = h->st[s];
+  const int n = si.n, cap = si.cap;
+  const double scale = std::pow(nrm, -1.0 / (n - 1));
+  QScratch q;
+  PT_CHECK(get_qscratch(h, cap, &q, (size_t)2 * n));
+  hipStream_t stream = h->stream;
+  const size_t blk = qscratch_elems(cap);
+  for (int site = 0; site < n; ++site) {
+    const int cl = si.dims[site], cm = si.dims[site + 1];
+    const double sl = (site >= 1) ? scale : 1.0;
+    const double sr = (site + 1 <= n - 1) ? scale : 1.0;
+    // A = Lambda[q] Gamma[q] and B = Gamma[q] Lambda[q+1] with the inner Lambdas scaled
+    site_a(h, s, site, h->lam_slot(s, site), nullptr, sl, 1.0, q.a);
+    site_a(h, s, site, nullptr, h->lam_slot(s, site + 1), 1.0, sr, q.b);
+    for (int p = 0; p < 2; ++p)
+      ptebd::launch_zgemm('C', 'N', cm, cm, cl, 1.0, q.a + (size_t)p * cl * cm, cl,
+                          q.a + (size_t)p * cl * cm, cl, p == 0 ? 0.0 : 1.0, q.e, cm, stream);
+    ptebd::launch_frob_minus_identity(q.e, cm, q.red + 2 * site, stream);
+    for (int p = 0; p < 2; ++p)
+      ptebd::launch_zgemm('N', 'C', cl, cl, cm, 1.0, q.b + (size_t)p * cl * cm, cl,
+                          q.b + (size_t)p * cl * cm, cl, p == 0 ? 0.0 : 1.0, q.e2, cl, stream);
+    ptebd::launch_frob_minus_identity(q.e2, cl, q.red + 2 * site + 1, stream);
+  }
+  (void)blk;
+  PT_HIP(hipGetLastError());
+  std::vector<double> red(2 * (size_t)n);
+  PT_HIP(hipMemcpyAsync(red.data(), q.red, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, stream));
+  PT_HIP(hipStreamSynchronize(stream));
+  double total = 0;
+  for (int i = 0; i < 2 * n; ++i) total += std::sqrt(red[i]);
+  *out = total / (2.0 * n);
+  return PTEBD_OK;
+}
+
+int ptebd_norm_estimate(ptebd_mps_t h, int s, double* out) {
+  PT_CHECK(check_state(h, s));
+  if (!out) return fail(PTEBD_EINVAL, "null output");
+  *out = h->st[s].prod_nu;
+  return PTEBD_OK;
+}
+
+int ptebd_fidelity_estimate(ptebd_mps_t h, int s, double* out) {
+  PT_CHECK(check_state(h, s));
+  if (!out) return fail(PTEBD_EINVAL, "null output");
+  *out = h->st[s].prod_fid;
+  return PTEBD_OK;
+}
+
+int ptebd_bond_dims(ptebd_mps_t h, int s, int32_t* out, int cap) {
+  PT_CHECK(check_state(h, s));
+  const StateInfo& si = h->st[s];
+  if (!out || cap < si.n + 1) return fail(PTEBD_EINVAL, "output too small");
+  for (int i = 0; i <= si.n; ++i) out[i] = si.dims[i];
+  return PTEBD_OK;
+}
+
+int ptebd_get_lambda(ptebd_mps_t h, int s, int bond, double* out, int cap, int* len) {
+  PT_CHECK(check_state(h, s));
+  const StateInfo& si = h->st[s];
+  if (bond < 0 || bond > si.n) return fail(PTEBD_EINVAL, "bond out of range");
+  const int chi = si.dims[bond];
+  if (len) *len = chi;
+  if (!out || cap < chi) return fail(PTEBD_EINVAL, "output too small");
+  PT_CHECK(set_device(h));
+  PT_HIP(hipMemcpyAsync(out, h->lam_slot(s, bond), sizeof(double) * chi, hipMemcpyDeviceToHost,
+                        h->stream));
+  PT_HIP(hipStreamSynchronize(h->stream));
+  return PTEBD_OK;
+}
+
+int ptebd_export(ptebd_mps_t h, int s, double* gamma, size_t gamma_cap, double* lambda,
+                 size_t lambda_cap) {
+  PT_CHECK(check_state(h, s));
+  const StateInfo& si = h->st[s];
+  size_t need_g = 0, need_l = 0;
+  for (int q = 0; q < si.n; ++q) need_g += 2 * 2 * (size_t)si.dims[q] * si.dims[q + 1];
+  for (int i = 0; i <= si.n; ++i) need_l += si.dims[i];
+  if (!gamma || !lambda || gamma_cap < need_g || lambda_cap < need_l)
+    return fail(PTEBD_EINVAL, "export buffers too small");
+  PT_CHECK(set_device(h));
+  PT_HIP(hipStreamSynchronize(h->stream));
+  std::vector<char> tmp;
+  size_t go = 0, lo = 0;
+  for (int q = 0; q < si.n; ++q) {
+    const int cl = si.dims[q], cm = si.dims[q + 1];
+    const size_t cnt = 2 * (size_t)cl * cm;
+    tmp.resize(cnt * h->celem);
+    PT_HIP(hipMemcpy(tmp.data(), h->gamma_slot(s, q), cnt * h->celem, hipMemcpyDeviceToHost));
+    for (int a = 0; a < cl; ++a)
+      for (int p = 0; p < 2; ++p)
+        for (int m = 0; m < cm; ++m) {
+          const size_t src = (size_t)p * cl * cm + (size_t)m * cl + a;
+          const size_t dst = go + 2 * (((size_t)a * 2 + p) * cm + m);
+          if (h->precision == PTEBD_FP64) {
+            const cplx<double> z = ((const cplx<double>*)tmp.data())[src];
+            gamma[dst] = z.re;
+            gamma[dst + 1] = z.im;
+          } else {
+            const cplx<float> z = ((const cplx<float>*)tmp.data())[src];
+            gamma[dst] = z.re;
+            gamma[dst + 1] = z.im;
+          }
+        }
+    go += 2 * cnt;
+  }
+  for (int i = 0; i <= si.n; ++i) {
+    PT_HIP(hipMemcpy(lambda + lo, h->lam_slot(s, i), sizeof(double) * si.dims[i], hipMemcpyDeviceToHost));
+    lo += si.dims[i];
+  }
+  return PTEBD_OK;
+}
+
+int ptebd_import(ptebd_mps_t h, int s, const int32_t* dims, const double* gamma,
+                 const double* lambda) {
+  PT_CHECK(check_state(h, s));
+  StateInfo& si = h->st[s];
+  if (!dims || !gamma || !lambda) return fail(PTEBD_EINVAL, "null input");
+  if (dims[0] != 1 || dims[si.n] != 1) return fail(PTEBD_EINVAL, "chi_0 and chi_N must be 1");
+  size_t need_g = 0, need_l = 0;
+  for (int i = 0; i <= si.n; ++i) {
+    if (dims[i] < 1 || dims[i] > si.cap) return fail(PTEBD_EINVAL, "bond dimension out of [1, chi_cap]");
+    need_l += dims[i];
+  }
+  for (int q = 0; q < si.n; ++q) need_g += 4 * (size_t)dims[q] * dims[q + 1];
+  if (!finite_all(gamma, need_g) || !finite_all(lambda, need_l))
+    return fail(PTEBD_EINVAL, "non-finite input");
+  PT_CHECK(set_device(h));
+  PT_HIP(hipStreamSynchronize(h->stream));
+  std::vector<char> tmp;
+  size_t go = 0, lo = 0;
+  for (int q = 0; q < si.n; ++q) {
+    const int cl = dims[q], cm = dims[q + 1];
+    const size_t cnt = 2 * (size_t)cl * cm;
+    tmp.resize(cnt * h->celem);
+    for (int a = 0; a < cl; ++a)
+      for (int p = 0; p < 2; ++p)
+        for (int m = 0; m < cm; ++m) {
+          const size_t dst = (size_t)p * cl * cm + (size_t)m * cl + a;
+          const size_t src = go + 2 * (((size_t)a * 2 + p) * cm + m);
+          if (h->precision == PTEBD_FP64) {
+            cplx<double>& z = ((cplx<double>*)tmp.data())[dst];
+            z.re = gamma[src];
+            z.im = gamma[src + 1];
+          } else {
+            cplx<float>& z = ((cplx<float>*)tmp.data())[dst];
+            z.re = (float)gamma[src];
+            z.im = (float)gamma[src + 1];
+          }
+        }
+    PT_HIP(hipMemcpy(h->gamma_slot(s, q), tmp.data(), cnt * h->celem, hipMemcpyHostToDevice));
+    go += 2 * cnt;
+  }
+  for (int i = 0; i <= si.n; ++i) {
+    PT_HIP(hipMemcpy(h->lam_slot(s, i), lambda + lo, sizeof(double) * dims[i], hipMemcpyHostToDevice));
+    lo += dims[i];
+  }
+  for (int i = 0; i <= si.n; ++i) si.dims[i] = dims[i];
+  si.prod_nu = 1.0;
+  si.prod_fid = 1.0;
+  return PTEBD_OK;
+}
+
+int ptebd_debug_theta(ptebd_mps_t h, int s, int q, const double* gate, double* out) {
+  PT_CHECK(check_state(h, s));
+  StateInfo& si = h->st[s];
+  if (q < 0 || q + 1 >= si.n) return fail(PTEBD_EINVAL, "bond q out of range");
+  if (!out) return fail(PTEBD_EINVAL, "null output");
+  if (gate && !finite_all(gate, 32)) return fail(PTEBD_EINVAL, "non-finite gate entry");
+  PT_CHECK(set_device(h));
+  const int cl = si.dims[q], cm = si.dims[q + 1], cr = si.dims[q + 2];
+  GateDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.cl = cl;
+  d.cm = cm;
+  d.cr = cr;
+  const int m = 2 * cl, nn = 2 * cr;
+  d.transposed = nn > m;
+  d.R = std::max(m, nn);
+  d.C = std::min(m, nn);
+  d.has_gate = gate ? 1 : 0;
+  d.gq = h->gamma_slot(s, q);
+  d.gq1 = h->gamma_slot(s, q + 1);
+  d.lam_l = h->lam_slot(s, q);
+  d.lam_m = h->lam_slot(s, q + 1);
+  d.lam_r = h->lam_slot(s, q + 2);
+  const size_t welems = (size_t)d.R * d.C;
+  PT_CHECK(h->work.ensure(welems * h->celem));
+  PT_CHECK(h->desc.ensure(sizeof(GateDesc)));
+  PT_CHECK(h->gates.ensure(sizeof(double) * 32));
+  d.w = h->work.p;
+  d.gate = gate ? (const double*)h->gates.p : nullptr;
+  if (gate) PT_HIP(hipMemcpy(h->gates.p, gate, sizeof(double) * 32, hipMemcpyHostToDevice));
+  PT_HIP(hipMemcpy(h->desc.p, &d, sizeof(d), hipMemcpyHostToDevice));
+  const int tiles = ((cl + 31) / 32) * ((cr + 31) / 32);
+  if (h->precision == PTEBD_FP64)
+    ptebd::launch_theta<double>((const GateDesc*)h->desc.p, 1, tiles, h->stream);
+  else
+    ptebd::launch_theta<float>((const GateDesc*)h->desc.p, 1, tiles, h->stream);
+  PT_HIP(hipGetLastError());
+  PT_HIP(hipStreamSynchronize(h->stream));
+  std::vector<char> tmp(welems * h->celem);
+  PT_HIP(hipMemcpy(tmp.data(), h->work.p, tmp.size(), hipMemcpyDeviceToHost));
+  // device row index s' * chi_q + a  ->  documented row index a * 2 + s'
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < nn; ++c) {
+      const size_t src = d.transposed ? (size_t)r * d.R + c : (size_t)c * d.R + r;
+      const int a = r % cl, sp = r / cl;
+      const size_t orow = (size_t)a * 2 + sp;
+      double re, im;
+      if (h->precision == PTEBD_FP64) {
+        const cplx<double> z = ((const cplx<double>*)tmp.data())[src];
+        re = z.re;
+        im = z.im;
+      } else {
+        const cplx<float> z = ((const cplx<float>*)tmp.data())[src];
+        re = z.re;
+        im = z.im;
+      }
+      if (d.transposed) im = -im;
+      out[2 * (orow * nn + c)] = re;
+      out[2 * (orow * nn + c) + 1] = im;
+    }
+  return PTEBD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <class T>
+int svd_batched_t(int precision, int batch, int m, int n, const double* a, double* s, double* u,
+                  double* vh, int32_t* sweeps, int max_sweeps, double tol_factor,
+                  hipStream_t stream) {
+  const bool tr = n > m;
+  const int R = std::max(m, n), C = std::min(m, n);
+  const size_t wel = (size_t)R * C, vel = (size_t)C * C;
+  DevBuf work, desc, outb;
+  PT_CHECK(work.ensure(sizeof(cplx<T>) * (wel + vel) * batch));
+  PT_CHECK(desc.ensure(sizeof(GateDesc) * batch));
+  const OutLayout L = out_layout(batch, C);
+  PT_CHECK(outb.ensure(L.total));
+  std::vector<cplx<T>> hw(wel * batch);
+  for (int b = 0; b < batch; ++b)
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double re = a[2 * (((size_t)b * m + i) * n + j)];
+        const double im = a[2 * (((size_t)b * m + i) * n + j) + 1];
+        cplx<T> z;
+        z.re = (T)re;
+        if (!tr) {
+          z.im = (T)im;
+          hw[b * wel + (size_t)j * R + i] = z;
+        } else {
+          z.im = (T)(-im);
+          hw[b * wel + (size_t)i * R + j] = z;
+        }
+      }
+  std::vector<GateDesc> d(batch);
+  for (int b = 0; b < batch; ++b) {
+    std::memset(&d[b], 0, sizeof(GateDesc));
+    d[b].R = R;
+    d[b].C = C;
+    d[b].transposed = tr;
+    d[b].w = (char*)work.p + sizeof(cplx<T>) * wel * b;
+    d[b].v = (char*)work.p + sizeof(cplx<T>) * (wel * batch + vel * b);
+    d[b].chi_max = 0;
+    d[b].stabilize = 0;
+    d[b].lam_m = nullptr;
+  }
+  auto cleanup = [&](int code) {
+    work.release();
+    desc.release();
+    outb.release();
+    return code;
+  };
+  if (hipMemcpy(work.p, hw.data(), sizeof(cplx<T>) * wel * batch, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(desc.p, d.data(), sizeof(GateDesc) * batch, hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(fail(PTEBD_EDEVICE, "upload failed"));
+  const LayerOut lo = make_layer_out(outb.p, L, C);
+  int32_t counter = 0;
+  int n_unconv = 0;
+  int st = run_jacobi<T>(stream, (const GateDesc*)desc.p, batch, C, lo, precision, max_sweeps,
+                         tol_factor, 2, &counter, &n_unconv, nullptr);
+  if (st < 0) return cleanup(st);
+  ptebd::launch_finalize<T>((const GateDesc*)desc.p, batch, 0.0, lo, stream);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+    return cleanup(fail(PTEBD_EDEVICE, "svd kernels failed"));
+  std::vector<double> sig((size_t)batch * C);
+  std::vector<int32_t> perm((size_t)batch * C), sw(batch);
+  std::vector<cplx<T>> hv(vel * batch);
+  if (hipMemcpy(sig.data(), lo.sig, sizeof(double) * batch * C, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(perm.data(), lo.perm, sizeof(int32_t) * batch * C, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(sw.data(), lo.sweeps, sizeof(int32_t) * batch, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hw.data(), work.p, sizeof(cplx<T>) * wel * batch, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(hv.data(), (char*)work.p + sizeof(cplx<T>) * wel * batch, sizeof(cplx<T>) * vel * batch,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return cleanup(fail(PTEBD_EDEVICE, "download failed"));
+  for (int b = 0; b < batch; ++b) {
+    for (int j = 0; j < C; ++j) {
+      const double sj = sig[(size_t)b * C + j];
+      const int pj = perm[(size_t)b * C + j];
+      s[(size_t)b * C + j] = sj;
+      const double inv = sj > 0 ? 1.0 / sj : 0.0;
+      // left vectors (m rows) and right vectors (n columns of vh)
+      for (int i = 0; i < m; ++i) {
+        double re, im;
+        if (!tr) {
+          const cplx<T> z = hw[b * wel + (size_t)pj * R + i];
+          re = z.re * inv;
+          im = z.im * inv;
+        } else {
+          const cplx<T> z = hv[b * vel + (size_t)pj * C + i];
+          re = z.re;
+          im = z.im;
+        }
+        if (u) {
+          u[2 * (((size_t)b * m + i) * C + j)] = re;
+          u[2 * (((size_t)b * m + i) * C + j) + 1] = im;
+        }
+      }
+      for (int i = 0; i < n; ++i) {
+        double re, im;
+        if (!tr) {
+          const cplx<T> z = hv[b * vel + (size_t)pj * C + i];
+          re = z.re;
+          im = -z.im;
+        } else {
+          const cplx<T> z = hw[b * wel + (size_t)pj * R + i];
+          re = z.re * inv;
+          im = -z.im * inv;
+        }
+        if (vh) {
+          vh[2 * (((size_t)b * C + j) * n + i)] = re;
+          vh[2 * (((size_t)b * C + j) * n + i) + 1] = im;
+        }
+      }
+    }
+    if (sweeps) sweeps[b] = sw[b];
+  }
+  cleanup(0);
+  if (n_unconv > 0) return fail(PTEBD_WNOCONV, "some SVDs reached the sweep cap");
+  return PTEBD_OK;
+}
+
+}  // namespace
+
+extern "C" int ptebd_svd_batched(int precision, int batch, int m, int n, const double* a,
+                                 double* s, double* u, double* vh, int32_t* sweeps,
+                                 int max_sweeps, double tol_factor, void* hip_stream) {
+  if (precision != PTEBD_FP64 && precision != PTEBD_FP32) return fail(PTEBD_EINVAL, "bad precision");
+  if (batch < 1 || m < 1 || n < 1 || std::min(m, n) > 1024 || batch > 65535)
+    return fail(PTEBD_EINVAL, "bad sizes (batch in [1, 65535], min(m, n) <= 1024)");
+  if (!a || !s) return fail(PTEBD_EINVAL, "null input / output");
+  if (max_sweeps < 1 || !(tol_factor > 0.0)) return fail(PTEBD_EINVAL, "bad sweep controls");
+  if (!finite_all(a, 2 * (size_t)batch * m * n)) return fail(PTEBD_EINVAL, "non-finite input");
+  if (precision == PTEBD_FP64)
+    return svd_batched_t<double>(precision, batch, m, n, a, s, u, vh, sweeps, max_sweeps,
+                                 tol_factor, (hipStream_t)hip_stream);
+  return svd_batched_t<float>(precision, batch, m, n, a, s, u, vh, sweeps, max_sweeps, tol_factor,
+                              (hipStream_t)hip_stream);
+}

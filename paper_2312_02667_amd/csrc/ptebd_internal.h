@@ -1,0 +1,108 @@
+// Internal declarations shared by the host runtime and the HIP kernels of libptebd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ptebd {
+
+// Complex number of precision T, stored interleaved (re, im).
+template <class T>
+struct alignas(2 * sizeof(T)) cplx {
+  T re, im;
+};
+
+// Device descriptor of one bond update (one gate, or one tSU) of a layer.
+//
+// Device layout of Gamma[q] (shape chi_q x 2 x chi_{q+1}): two planes s = 0, 1, each a
+// column-major chi_q x chi_{q+1} matrix (row a fastest); element (a, s, m) at
+// s * chi_q * chi_{q+1} + m * chi_q + a, complex of the handle's precision.
+//
+// The two-site wavefunction theta is the (2 chi_q) x (2 chi_{q+2}) matrix with row index
+// s' * chi_q + a and column index t' * chi_{q+2} + c.  The SVD works on the column-major
+// work matrix W with R rows and C <= R columns: W = theta when 2 chi_{q+2} <= 2 chi_q,
+// else W = theta^H (transposed = 1).  V is the C x C matrix of accumulated rotations.
+struct GateDesc {
+  int32_t cl, cm, cr;      // chi_q, chi_{q+1}, chi_{q+2}
+  int32_t R, C;            // rows / columns of W
+  int32_t transposed;      // 1: W = theta^H
+  int32_t has_gate;        // 0: identity gate (tSU), the gate mix is skipped
+  int32_t chi_max;         // truncation bound; <= 0: keep every sigma above the cutoff
+  int32_t stabilize;       // 1: nu = (1 - eps)^(-1/2); 0: nu = 1
+  int32_t pad_;
+  void* gq;                // Gamma[q] slot
+  void* gq1;               // Gamma[q+1] slot
+  const double* lam_l;     // Lambda[q]   (cl)
+  double* lam_m;           // Lambda[q+1] (written: k values)
+  const double* lam_r;     // Lambda[q+2] (cr)
+  void* w;                 // R x C work matrix (complex T)
+  void* v;                 // C x C rotation matrix (complex T)
+  const double* gate;      // 16 complex128, U[(s' t'), (s t)] row-major
+};
+
+// Per-gate outputs of a layer's SVD + truncation, device arrays of length n_gates
+// (sig / perm: n_gates * cmax).
+struct LayerOut {
+  double* sig;       // singular values, descending
+  int32_t* perm;     // column of W holding the j-th largest
+  int32_t* k;        // kept dimension
+  int32_t* r;        // rank above the cutoff
+  double* eps;       // discarded weight
+  double* nu;        // stabilization factor
+  int32_t* sweeps;   // Jacobi sweeps
+  int32_t* conv;     // converged flag
+  uint32_t* offbits; // max relative off-diagonal of the sweep (float bits)
+  int32_t* counters; // [0..1] unconverged counts (double-buffered by sweep parity),
+                     // [2] error flags: bit0 annihilated, bit1 non-finite
+  unsigned long long* work;  // executed Jacobi work: [0] sum R over Gram pairs,
+                             // [1] sum (R + C) over rotated pairs, [2] Gram pairs,
+                             // [3] rotated pairs
+  int32_t cmax;
+};
+
+// Kernel launchers (ptebd_kernels.hip).  All are asynchronous on `stream`.
+template <class T>
+void launch_theta(const GateDesc* d_desc, int n_gates, int max_tiles, hipStream_t stream);
+template <class T>
+void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
+                         const LayerOut& out, double tol_scale, int inner_sweeps,
+                         hipStream_t stream);
+void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
+                        double unit_roundoff, const LayerOut& out, hipStream_t stream);
+template <class T>
+void launch_jacobi_init(const GateDesc* d_desc, int n_gates, int max_c, const LayerOut& out,
+                        hipStream_t stream);
+template <class T>
+void launch_finalize(const GateDesc* d_desc, int n_gates, double cutoff, const LayerOut& out,
+                     hipStream_t stream);
+template <class T>
+void launch_writeback(const GateDesc* d_desc, int n_gates, const LayerOut& out,
+                      hipStream_t stream);
+
+// Query kernels (ptebd_queries.hip), all FP64.
+// Column-major complex GEMM C = alpha * op(A) * op(B) + beta * C, op: 'N', 'T' or 'C'.
+void launch_zgemm(char opa, char opb, int m, int n, int k, double alpha_re,
+                  const cplx<double>* a, int lda, const cplx<double>* b, int ldb,
+                  double beta_re, cplx<double>* c, int ldc, hipStream_t stream);
+// A_s = diag(lam) * Gamma_s for both planes, converted to FP64: out planes (cl x cm) each.
+template <class T>
+void launch_site_a(const void* gamma, const double* lam_left, const double* lam_right,
+                   int cl, int cm, double scale_left, double scale_right, cplx<double>* out,
+                   hipStream_t stream);
+// out[0] = sum_ij |x_ij - delta_ij|^2 of an n x n matrix (canonical distance).
+void launch_frob_minus_identity(const cplx<double>* x, int n, double* out, hipStream_t stream);
+// out[0] += weight * Re sum_i conj(a_i) b_i (used by <Z>).
+void launch_dot_conj(const cplx<double>* a, const cplx<double>* b, int count, double weight,
+                     double* out_re, hipStream_t stream);
+// x[0] = value (a 1 x 1 environment).
+void launch_set_identity_scalar(cplx<double>* x, double value, hipStream_t stream);
+// |0...0>: Gamma[q] = e_0 at the listed Gamma slots (byte offsets), Lambda = (1) at the
+// listed Lambda slots (double offsets).
+template <class T>
+void launch_init_product(void* gamma_base, const size_t* d_gamma_offsets, int n_sites,
+                         double* lam_base, const size_t* d_lam_offsets, int n_bonds,
+                         hipStream_t stream);
+
+}  // namespace ptebd

@@ -1,0 +1,755 @@
+// HIP kernels of one pTEBD layer on gfx950:
+//   theta_kernel     -- two-site wavefunction (Sec. II.C) as complex GEMMs on MFMA
+//   jacobi_*         -- batched one-sided block Jacobi SVD (Hestenes), MFMA Gram and
+//                       column updates, FP64 inner rotations
+//   finalize_kernel  -- singular values, sort, truncation and discarded weight (Sec. III.B,
+//                       Theorem 1), norm stabilization nu (Sec. III.C.2, Eq. (lren))
+//   writeback_kernel -- Vidal regauge with Lambda^{-1} (Sec. II.C) into the state arena
+#include "ptebd_internal.h"
+
+namespace ptebd {
+namespace {
+
+// ---------------------------------------------------------------- MFMA wrappers
+// 16x16x4 MFMA.  Operand lane layout (both precisions): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16].  Result: 4 values per lane in column l%16; their rows differ between the
+// f32 and f64 instructions (checked on gfx950): f32 rows 4*(l/16)+v, f64 rows l/16+4v.
+template <class T>
+struct Mfma;
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+// acc += a * b (complex); acc[0] real part, acc[1] imaginary part.
+template <class T>
+__device__ inline void cmfma(typename Mfma<T>::v4 (&acc)[2], cplx<T> a, cplx<T> b) {
+  acc[0] = Mfma<T>::op(a.re, b.re, acc[0]);
+  acc[0] = Mfma<T>::op(-a.im, b.im, acc[0]);
+  acc[1] = Mfma<T>::op(a.re, b.im, acc[1]);
+  acc[1] = Mfma<T>::op(a.im, b.re, acc[1]);
+}
+
+// acc += conj(x) * y (complex), the Gram-matrix update.
+template <class T>
+__device__ inline void gram_mfma(typename Mfma<T>::v4 (&acc)[2], cplx<T> x, cplx<T> y) {
+  acc[0] = Mfma<T>::op(x.re, y.re, acc[0]);
+  acc[0] = Mfma<T>::op(x.im, y.im, acc[0]);
+  acc[1] = Mfma<T>::op(x.re, y.im, acc[1]);
+  acc[1] = Mfma<T>::op(-x.im, y.re, acc[1]);
+}
+
+template <class T>
+__device__ inline cplx<T> czero() {
+  cplx<T> z;
+  z.re = T(0);
+  z.im = T(0);
+  return z;
+}
+
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Round-robin (circle method) tournament: player in `slot` during `round`, for an even
+// number of players; slot 0 is fixed, the others rotate.  Pairs are (p, nplayers-1-p).
+__device__ inline int rr_player(int slot, int round, int nplayers) {
+  return slot == 0 ? 0 : 1 + ((slot - 1 + round) % (nplayers - 1));
+}
+
+// ---------------------------------------------------------------- theta
+// One workgroup computes a 32 (a) x 32 (c) tile of the four products
+// M_st = A_s B_t, A_s = diag(Lambda[q]) Gamma[q]_s diag(Lambda[q+1]) (chi_q x chi_{q+1}),
+// B_t = Gamma[q+1]_t diag(Lambda[q+2]) (chi_{q+1} x chi_{q+2}), then mixes them with the
+// gate: theta[(s',a),(t',c)] = sum_st U[(s't'),(st)] M_st[a,c].  Four waves, each a 16x16
+// sub-tile of all four products; K (= chi_{q+1}) staged through LDS in steps of 16.
+template <class T>
+__global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__ descs) {
+  const GateDesc* d = descs + blockIdx.y;
+  const int cl = d->cl, cm = d->cm, cr = d->cr;
+  const int tiles_c = (cr + 31) >> 5;
+  const int tiles = ((cl + 31) >> 5) * tiles_c;
+  if ((int)blockIdx.x >= tiles) return;
+  const int a0 = (blockIdx.x / tiles_c) * 32, c0 = (blockIdx.x % tiles_c) * 32;
+
+  __shared__ cplx<T> As[2][16][33];
+  __shared__ cplx<T> Bs[2][16][33];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wa = wave >> 1, wc = wave & 1;
+  typedef typename Mfma<T>::v4 V4;
+  V4 acc[4][2];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+
+  const cplx<T>* __restrict__ gq = (const cplx<T>*)d->gq;
+  const cplx<T>* __restrict__ gq1 = (const cplx<T>*)d->gq1;
+  const double* __restrict__ lam_l = d->lam_l;
+  const double* __restrict__ lam_m = d->lam_m;
+  const double* __restrict__ lam_r = d->lam_r;
+  const size_t plane_a = (size_t)cl * cm, plane_b = (size_t)cm * cr;
+
+  for (int k0 = 0; k0 < cm; k0 += 16) {
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + 256 * i;
+      const int s = e >> 9, rem = e & 511;
+      {  // A tile: rows a (fastest in memory), k
+        const int k = rem >> 5, a = rem & 31;
+        const int ga = a0 + a, gk = k0 + k;
+        cplx<T> val = czero<T>();
+        if (ga < cl && gk < cm) {
+          const cplx<T> g = gq[s * plane_a + (size_t)gk * cl + ga];
+          const double sc = lam_l[ga] * lam_m[gk];
+          val.re = (T)((double)g.re * sc);
+          val.im = (T)((double)g.im * sc);
+        }
+        As[s][k][a] = val;
+      }
+      {  // B tile: rows k (fastest in memory), columns c
+        const int c = rem >> 4, k = rem & 15;
+        const int gc = c0 + c, gk = k0 + k;
+        cplx<T> val = czero<T>();
+        if (gc < cr && gk < cm) {
+          const cplx<T> g = gq1[s * plane_b + (size_t)gc * cm + gk];
+          const double sc = lam_r[gc];
+          val.re = (T)((double)g.re * sc);
+          val.im = (T)((double)g.im * sc);
+        }
+        Bs[s][k][c] = val;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      const cplx<T> a0v = As[0][kk][wa * 16 + (lane & 15)];
+      const cplx<T> a1v = As[1][kk][wa * 16 + (lane & 15)];
+      const cplx<T> b0v = Bs[0][kk][wc * 16 + (lane & 15)];
+      const cplx<T> b1v = Bs[1][kk][wc * 16 + (lane & 15)];
+      cmfma<T>(acc[0], a0v, b0v);
+      cmfma<T>(acc[1], a0v, b1v);
+      cmfma<T>(acc[2], a1v, b0v);
+      cmfma<T>(acc[3], a1v, b1v);
+    }
+    __syncthreads();
+  }
+
+  const int has_gate = d->has_gate, transposed = d->transposed, R = d->R;
+  T ur[16], ui[16];
+  if (has_gate) {
+    for (int i = 0; i < 16; ++i) {
+      ur[i] = (T)d->gate[2 * i];
+      ui[i] = (T)d->gate[2 * i + 1];
+    }
+  }
+  cplx<T>* __restrict__ w = (cplx<T>*)d->w;
+  for (int v = 0; v < 4; ++v) {
+    const int a = a0 + wa * 16 + Mfma<T>::row(lane, v);
+    const int c = c0 + wc * 16 + (lane & 15);
+    if (a >= cl || c >= cr) continue;
+    T mr[4], mi[4];
+    for (int st = 0; st < 4; ++st) {
+      mr[st] = acc[st][0][v];
+      mi[st] = acc[st][1][v];
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+      for (int tp = 0; tp < 2; ++tp) {
+        T tr, ti;
+        if (has_gate) {
+          tr = T(0);
+          ti = T(0);
+          const int row = (sp * 2 + tp) * 4;
+          for (int st = 0; st < 4; ++st) {
+            tr += ur[row + st] * mr[st] - ui[row + st] * mi[st];
+            ti += ur[row + st] * mi[st] + ui[row + st] * mr[st];
+          }
+        } else {
+          tr = mr[sp * 2 + tp];
+          ti = mi[sp * 2 + tp];
+        }
+        const int row = sp * cl + a, col = tp * cr + c;
+        cplx<T> o;
+        o.re = tr;
+        if (!transposed) {
+          o.im = ti;
+          w[(size_t)col * R + row] = o;
+        } else {
+          o.im = -ti;
+          w[(size_t)row * R + col] = o;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Jacobi
+// V = I (C x C), per-gate convergence state cleared.
+template <class T>
+__global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut out) {
+  const int g = blockIdx.y;
+  const GateDesc* d = descs + g;
+  const int C = d->C;
+  cplx<T>* v = (cplx<T>*)d->v;
+  const size_t total = (size_t)C * C;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t col = e / C, row = e % C;
+    cplx<T> z = czero<T>();
+    if (row == col) z.re = T(1);
+    v[e] = z;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out.conv[g] = 0;
+    out.sweeps[g] = 0;
+    out.offbits[g] = 0u;
+    if (g == 0) {
+      out.counters[0] = 0;
+      out.counters[1] = 0;
+      out.counters[2] = 0;
+      for (int i = 0; i < 4; ++i) out.work[i] = 0ull;
+    }
+  }
+}
+
+// One round of the block Jacobi sweep: every workgroup takes one pair (I, J) of 16-column
+// blocks of one gate's W, forms the 32x32 Gram matrix G = W_IJ^H W_IJ on MFMA, records the
+// largest relative off-diagonal |G_ij| / sqrt(G_ii G_jj), diagonalizes G by cyclic Jacobi
+// rotations in FP64 (angles and accumulated rotation Q in FP64), and applies Q to the 32
+// columns of W and of V on MFMA.  Pairs of one round are disjoint, so no two workgroups of
+// a gate touch the same column.
+template <class T>
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
+                                                           int round, int nbp, LayerOut out,
+                                                           double tol_scale, int inner_sweeps) {
+  const int g = blockIdx.y;
+  if (out.conv[g]) return;
+  const GateDesc* d = descs + g;
+  const int R = d->R, C = d->C;
+  const int nb = (C + 15) >> 4;
+  const int I = rr_player(blockIdx.x, round, nbp);
+  const int J = rr_player(nbp - 1 - blockIdx.x, round, nbp);
+  const bool dummy_i = I >= nb, dummy_j = J >= nb;
+  if (dummy_i && dummy_j) return;
+  // A pair with the padding player is skipped, except when the matrix has a single block:
+  // then that block is diagonalized on its own against an empty second half.
+  if ((dummy_i || dummy_j) && nb > 1) return;
+  const int cI = dummy_i ? 0 : I * 16, cJ = dummy_j ? 0 : J * 16;
+  const int nI = dummy_i ? 0 : min(16, C - cI), nJ = dummy_j ? 0 : min(16, C - cJ);
+  cplx<T>* __restrict__ W = (cplx<T>*)d->w;
+  cplx<T>* __restrict__ V = (cplx<T>*)d->v;
+
+  __shared__ cplx<double> G[32][33];
+  __shared__ cplx<double> Q[32][33];
+  __shared__ union {
+    cplx<double> part[2][3][16][17];
+    cplx<T> qt[32][33];
+  } U;
+  __shared__ double rot_c[16];
+  __shared__ cplx<double> rot_s[16];
+  __shared__ double red[4];
+  __shared__ int flag;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  typedef typename Mfma<T>::v4 V4;
+
+  // ---- Gram matrix, rows split over the four waves in chunks of 16
+  V4 acc[3][2];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+  const bool okI = col < nI, okJ = col < nJ;
+  const cplx<T>* __restrict__ wI = W + (size_t)(cI + (okI ? col : 0)) * R;
+  const cplx<T>* __restrict__ wJ = W + (size_t)(cJ + (okJ ? col : 0)) * R;
+  for (int r0 = wave * 16; r0 < R; r0 += 64) {
+    cplx<T> xi[4], xj[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = r0 + grp * 4 + t;
+      const bool ok = r < R;
+      xi[t] = (okI && ok) ? wI[r] : czero<T>();
+      xj[t] = (okJ && ok) ? wJ[r] : czero<T>();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      gram_mfma<T>(acc[0], xi[t], xi[t]);
+      gram_mfma<T>(acc[1], xi[t], xj[t]);
+      gram_mfma<T>(acc[2], xj[t], xj[t]);
+    }
+  }
+  if (wave < 2) {
+    for (int tl = 0; tl < 3; ++tl)
+      for (int v = 0; v < 4; ++v) {
+        cplx<double> z;
+        z.re = (double)acc[tl][0][v];
+        z.im = (double)acc[tl][1][v];
+        U.part[wave][tl][Mfma<T>::row(lane, v)][col] = z;
+      }
+  }
+  __syncthreads();
+  if (wave >= 2) {
+    for (int tl = 0; tl < 3; ++tl)
+      for (int v = 0; v < 4; ++v) {
+        cplx<double>& z = U.part[wave - 2][tl][Mfma<T>::row(lane, v)][col];
+        z.re += (double)acc[tl][0][v];
+        z.im += (double)acc[tl][1][v];
+      }
+  }
+  __syncthreads();
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e >> 5, j = e & 31;
+    cplx<double> val;
+    if (i < 16 && j < 16) {
+      val.re = U.part[0][0][i][j].re + U.part[1][0][i][j].re;
+      val.im = U.part[0][0][i][j].im + U.part[1][0][i][j].im;
+    } else if (i < 16) {
+      val.re = U.part[0][1][i][j - 16].re + U.part[1][1][i][j - 16].re;
+      val.im = U.part[0][1][i][j - 16].im + U.part[1][1][i][j - 16].im;
+    } else if (j >= 16) {
+      val.re = U.part[0][2][i - 16][j - 16].re + U.part[1][2][i - 16][j - 16].re;
+      val.im = U.part[0][2][i - 16][j - 16].im + U.part[1][2][i - 16][j - 16].im;
+    } else {
+      val.re = U.part[0][1][j][i - 16].re + U.part[1][1][j][i - 16].re;
+      val.im = -(U.part[0][1][j][i - 16].im + U.part[1][1][j][i - 16].im);
+    }
+    G[i][j] = val;
+  }
+  __syncthreads();
+
+  // ---- convergence measure of this pair
+  double mx = 0.0;
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e >> 5, j = e & 31;
+    if (i < j) {
+      const double di = G[i][i].re, dj = G[j][j].re;
+      if (di > 0.0 && dj > 0.0) mx = fmax(mx, hypot(G[i][j].re, G[i][j].im) / sqrt(di * dj));
+    }
+  }
+  mx = wave_max(mx);
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const bool rotate = mx > tol_scale * sqrt((double)R);
+  if (tid == 0) {
+    atomicMax(&out.offbits[g], __float_as_uint((float)mx));
+    atomicAdd(&out.work[0], (unsigned long long)R);
+    atomicAdd(&out.work[2], 1ull);
+    if (rotate) {
+      atomicAdd(&out.work[1], (unsigned long long)(R + C));
+      atomicAdd(&out.work[3], 1ull);
+    }
+  }
+  if (!rotate) return;  // uniform: every thread read the same red[]
+
+  // ---- cyclic Jacobi on the 32x32 Hermitian G, FP64, Q accumulates the rotations
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e >> 5, j = e & 31;
+    cplx<double> z;
+    z.re = (i == j) ? 1.0 : 0.0;
+    z.im = 0.0;
+    Q[i][j] = z;
+  }
+  for (int sw = 0; sw < inner_sweeps; ++sw) {
+    __syncthreads();
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int rd = 0; rd < 31; ++rd) {
+      if (tid < 16) {
+        const int p = rr_player(tid, rd, 32), q = rr_player(31 - tid, rd, 32);
+        const double a = G[p][p].re, b = G[q][q].re;
+        const cplx<double> gg = G[p][q];
+        const double ag = hypot(gg.re, gg.im);
+        double c = 1.0, sr = 0.0, si = 0.0;
+        if (ag > 0.0 && ag > 1e-15 * sqrt(fmax(a * b, 0.0))) {
+          const double zeta = (b - a) / (2.0 * ag);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          const double s = t * c;
+          sr = s * gg.re / ag;
+          si = s * gg.im / ag;
+          flag = 1;
+        }
+        rot_c[tid] = c;
+        rot_s[tid].re = sr;
+        rot_s[tid].im = si;
+      }
+      __syncthreads();
+      {
+        // thread -> 2x2 block (row pair a, column pair b); J_x = [[c, s], [-conj(s), c]]
+        const int ia = tid >> 4, ib = tid & 15;
+        const int pa = rr_player(ia, rd, 32), qa = rr_player(31 - ia, rd, 32);
+        const int pb = rr_player(ib, rd, 32), qb = rr_player(31 - ib, rd, 32);
+        const double ca = rot_c[ia], cb = rot_c[ib];
+        const cplx<double> sa = rot_s[ia], sb = rot_s[ib];
+        const cplx<double> b00 = G[pa][pb], b01 = G[pa][qb], b10 = G[qa][pb], b11 = G[qa][qb];
+        // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
+        cplx<double> x00, x01, x10, x11;
+        x00.re = cb * b00.re - (sb.re * b01.re + sb.im * b01.im);
+        x00.im = cb * b00.im - (sb.re * b01.im - sb.im * b01.re);
+        x10.re = cb * b10.re - (sb.re * b11.re + sb.im * b11.im);
+        x10.im = cb * b10.im - (sb.re * b11.im - sb.im * b11.re);
+        x01.re = (sb.re * b00.re - sb.im * b00.im) + cb * b01.re;
+        x01.im = (sb.re * b00.im + sb.im * b00.re) + cb * b01.im;
+        x11.re = (sb.re * b10.re - sb.im * b10.im) + cb * b11.re;
+        x11.im = (sb.re * b10.im + sb.im * b10.re) + cb * b11.im;
+        // B' = J_a^H X: row0 = c_a X[0,:] - s_a X[1,:];  row1 = conj(s_a) X[0,:] + c_a X[1,:]
+        cplx<double> n00, n01, n10, n11;
+        n00.re = ca * x00.re - (sa.re * x10.re - sa.im * x10.im);
+        n00.im = ca * x00.im - (sa.re * x10.im + sa.im * x10.re);
+        n01.re = ca * x01.re - (sa.re * x11.re - sa.im * x11.im);
+        n01.im = ca * x01.im - (sa.re * x11.im + sa.im * x11.re);
+        n10.re = (sa.re * x00.re + sa.im * x00.im) + ca * x10.re;
+        n10.im = (sa.re * x00.im - sa.im * x00.re) + ca * x10.im;
+        n11.re = (sa.re * x01.re + sa.im * x01.im) + ca * x11.re;
+        n11.im = (sa.re * x01.im - sa.im * x01.re) + ca * x11.im;
+        // Q' = Q J_b on rows pa, qa
+        const cplx<double> q00 = Q[pa][pb], q01 = Q[pa][qb], q10 = Q[qa][pb], q11 = Q[qa][qb];
+        cplx<double> m00, m01, m10, m11;
+        m00.re = cb * q00.re - (sb.re * q01.re + sb.im * q01.im);
+        m00.im = cb * q00.im - (sb.re * q01.im - sb.im * q01.re);
+        m10.re = cb * q10.re - (sb.re * q11.re + sb.im * q11.im);
+        m10.im = cb * q10.im - (sb.re * q11.im - sb.im * q11.re);
+        m01.re = (sb.re * q00.re - sb.im * q00.im) + cb * q01.re;
+        m01.im = (sb.re * q00.im + sb.im * q00.re) + cb * q01.im;
+        m11.re = (sb.re * q10.re - sb.im * q10.im) + cb * q11.re;
+        m11.im = (sb.re * q10.im + sb.im * q10.re) + cb * q11.im;
+        __syncthreads();  // every block read before any write
+        G[pa][pb] = n00;
+        G[pa][qb] = n01;
+        G[qa][pb] = n10;
+        G[qa][qb] = n11;
+        Q[pa][pb] = m00;
+        Q[pa][qb] = m01;
+        Q[qa][pb] = m10;
+        Q[qa][qb] = m11;
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    const int f = flag;
+    if (f == 0) break;
+  }
+  __syncthreads();
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e >> 5, j = e & 31;
+    cplx<T> z;
+    z.re = (T)Q[i][j].re;
+    z.im = (T)Q[i][j].im;
+    U.qt[i][j] = z;
+  }
+  __syncthreads();
+
+  // ---- column update [W_I W_J] <- [W_I W_J] Q and [V_I V_J] <- [V_I V_J] Q on MFMA
+  for (int pass = 0; pass < 2; ++pass) {
+    cplx<T>* __restrict__ M = pass == 0 ? W : V;
+    const int rows = pass == 0 ? R : C;
+    for (int r0 = wave * 16; r0 < rows; r0 += 64) {
+      const int r = r0 + col;
+      cplx<T> av[8];
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const int kk = ks * 4 + grp;
+        const bool ok = (kk < 16 ? kk < nI : kk - 16 < nJ) && r < rows;
+        const int cidx = kk < 16 ? cI + kk : cJ + kk - 16;
+        av[ks] = ok ? M[(size_t)cidx * rows + r] : czero<T>();
+      }
+      V4 o[2][2];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          for (int v = 0; v < 4; ++v) o[i][j][v] = T(0);
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const cplx<T> b0 = U.qt[ks * 4 + grp][col];
+        const cplx<T> b1 = U.qt[ks * 4 + grp][16 + col];
+        cmfma<T>(o[0], av[ks], b0);
+        cmfma<T>(o[1], av[ks], b1);
+      }
+      for (int jt = 0; jt < 2; ++jt) {
+        const int jj = jt * 16 + col;
+        const bool okc = jt == 0 ? jj < nI : jj - 16 < nJ;
+        const int cidx = jt == 0 ? cI + jj : cJ + jj - 16;
+        if (!okc) continue;
+        for (int v = 0; v < 4; ++v) {
+          const int rr = r0 + Mfma<T>::row(lane, v);
+          if (rr < rows) {
+            cplx<T> z;
+            z.re = o[jt][0][v];
+            z.im = o[jt][1][v];
+            M[(size_t)cidx * rows + rr] = z;
+          }
+        }
+      }
+    }
+  }
+}
+
+// After a sweep: a gate whose largest relative off-diagonal stayed at or below
+// tol_factor * u * sqrt(R) is converged.  counters[sweep & 1] counts the others.
+__global__ void sweep_check_kernel(const GateDesc* __restrict__ descs, int n_gates, int sweep,
+                                   double tol_factor, double unit_roundoff, LayerOut out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) out.counters[(sweep + 1) & 1] = 0;
+  if (g >= n_gates) return;
+  if (out.conv[g]) return;
+  out.sweeps[g] += 1;
+  const float off = __uint_as_float(out.offbits[g]);
+  out.offbits[g] = 0u;
+  const double tol = tol_factor * unit_roundoff * sqrt((double)descs[g].R);
+  if ((double)off <= tol)
+    out.conv[g] = 1;
+  else
+    atomicAdd(&out.counters[sweep & 1], 1);
+}
+
+// ---------------------------------------------------------------- finalize
+// sigma_j = |W_j| (FP64), descending sort with the column permutation, r = #{sigma >
+// cutoff sigma_1}, k = min(chi_max, r), eps = sum_{j >= k} sigma_j^2, nu = (1-eps)^(-1/2),
+// Lambda[q+1] = nu sigma[:k].
+template <class T>
+__global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restrict__ descs,
+                                                       double cutoff, LayerOut out) {
+  const int g = blockIdx.x;
+  const GateDesc* d = descs + g;
+  const int R = d->R, C = d->C;
+  const cplx<T>* __restrict__ W = (const cplx<T>*)d->w;
+  __shared__ double key[1024];
+  __shared__ int idx[1024];
+  __shared__ double red_d[4];
+  __shared__ int red_i[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int P = 1;
+  while (P < C) P <<= 1;
+  for (int j = wave; j < C; j += 4) {
+    double s = 0.0;
+    for (int r = lane; r < R; r += 64) {
+      const cplx<T> x = W[(size_t)j * R + r];
+      s += (double)x.re * (double)x.re + (double)x.im * (double)x.im;
+    }
+    s = wave_sum(s);
+    if (lane == 0) {
+      key[j] = s;
+      idx[j] = j;
+    }
+  }
+  for (int j = C + tid; j < P; j += 256) {
+    key[j] = -1.0;
+    idx[j] = j;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < (P >> 1); i += 256) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool descending = (lo & size) == 0;
+        const double klo = key[lo], khi = key[hi];
+        const bool sw = descending ? (klo < khi) : (klo > khi);
+        if (sw) {
+          key[lo] = khi;
+          key[hi] = klo;
+          const int t = idx[lo];
+          idx[lo] = idx[hi];
+          idx[hi] = t;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const double s1 = sqrt(fmax(key[0], 0.0));
+  int cnt = 0;
+  for (int j = tid; j < C; j += 256)
+    if (sqrt(fmax(key[j], 0.0)) > cutoff * s1) ++cnt;
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+  if (lane == 0) red_i[wave] = cnt;
+  __syncthreads();
+  const int r = red_i[0] + red_i[1] + red_i[2] + red_i[3];
+  const int chi_max = d->chi_max;
+  int k = chi_max > 0 ? min(chi_max, r) : r;
+  if (k < 1) k = 1;
+  double part = 0.0;
+  for (int j = k + tid; j < C; j += 256) part += fmax(key[j], 0.0);
+  part = wave_sum(part);
+  if (lane == 0) red_d[wave] = part;
+  __syncthreads();
+  const double eps = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+  const double nu = d->stabilize ? 1.0 / sqrt(1.0 - eps) : 1.0;
+  double* lam_m = d->lam_m;
+  for (int j = tid; j < C; j += 256) {
+    const double s = sqrt(fmax(key[j], 0.0));
+    out.sig[(size_t)g * out.cmax + j] = s;
+    out.perm[(size_t)g * out.cmax + j] = idx[j];
+    if (lam_m != nullptr && j < k) lam_m[j] = nu * s;
+  }
+  if (tid == 0) {
+    out.k[g] = k;
+    out.r[g] = r;
+    out.eps[g] = eps;
+    out.nu[g] = nu;
+    int err = 0;
+    if (!(s1 > 0.0) || (d->stabilize && !(eps < 1.0))) err |= 1;
+    if (!isfinite(s1) || !isfinite(eps) || !isfinite(nu)) err |= 2;
+    if (err) atomicOr(&out.counters[2], err);
+  }
+}
+
+// ---------------------------------------------------------------- write-back
+// Gamma[q][a, s', j] = X[(s',a), j] / Lambda[q]_a and
+// Gamma[q+1][j, t', c] = Ydag[j, (t',c)] / Lambda[q+2]_c for the k kept columns, where
+// X = W/sigma, Ydag = V^H (W = theta) or X = V, Ydag = (W/sigma)^H (W = theta^H).
+// blockIdx.z = 0 writes Gamma[q], 1 writes Gamma[q+1] (LDS-transposed 32x32 tiles).
+template <class T>
+__global__ __launch_bounds__(256) void writeback_kernel(const GateDesc* __restrict__ descs,
+                                                        LayerOut out) {
+  const int g = blockIdx.y;
+  const GateDesc* d = descs + g;
+  const int k = out.k[g];
+  const int cl = d->cl, cr = d->cr, R = d->R, C = d->C, transposed = d->transposed;
+  const double* __restrict__ sig = out.sig + (size_t)g * out.cmax;
+  const int* __restrict__ perm = out.perm + (size_t)g * out.cmax;
+  const cplx<T>* __restrict__ W = (const cplx<T>*)d->w;
+  const cplx<T>* __restrict__ V = (const cplx<T>*)d->v;
+  const int tid = threadIdx.x;
+  if (blockIdx.z == 0) {
+    const cplx<T>* __restrict__ L = transposed ? V : W;
+    const int ldl = transposed ? C : R;
+    const bool divsig = !transposed;
+    const double* __restrict__ lam_l = d->lam_l;
+    cplx<T>* __restrict__ gout = (cplx<T>*)d->gq;
+    const size_t total = 2 * (size_t)cl * k;
+    for (size_t e = (size_t)blockIdx.x * 256 + tid; e < total; e += (size_t)gridDim.x * 256) {
+      const int a = (int)(e % cl);
+      const size_t rest = e / cl;
+      const int j = (int)(rest % k), sp = (int)(rest / k);
+      const cplx<T> x = L[(size_t)perm[j] * ldl + sp * cl + a];
+      double sc = 1.0 / lam_l[a];
+      if (divsig) sc /= sig[j];
+      cplx<T> z;
+      z.re = (T)((double)x.re * sc);
+      z.im = (T)((double)x.im * sc);
+      gout[(size_t)sp * cl * k + (size_t)j * cl + a] = z;
+    }
+  } else {
+    __shared__ cplx<T> tile[32][33];
+    const cplx<T>* __restrict__ Rs = transposed ? W : V;
+    const int ldr = transposed ? R : C;
+    const bool divsig = transposed;
+    const double* __restrict__ lam_r = d->lam_r;
+    cplx<T>* __restrict__ gout = (cplx<T>*)d->gq1;
+    const int tj = (k + 31) >> 5, tc = (cr + 31) >> 5;
+    const int ntiles = 2 * tj * tc;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      const int tp = t / (tj * tc), rem = t % (tj * tc);
+      const int j0 = (rem / tc) * 32, c0 = (rem % tc) * 32;
+      for (int i = 0; i < 4; ++i) {
+        const int e = tid + 256 * i;
+        const int jj = e >> 5, cc = e & 31;
+        const int j = j0 + jj, c = c0 + cc;
+        if (j < k && c < cr) {
+          const cplx<T> x = Rs[(size_t)perm[j] * ldr + tp * cr + c];
+          double sc = 1.0 / lam_r[c];
+          if (divsig) sc /= sig[j];
+          cplx<T> z;
+          z.re = (T)((double)x.re * sc);
+          z.im = (T)(-(double)x.im * sc);
+          tile[jj][cc] = z;
+        }
+      }
+      __syncthreads();
+      for (int i = 0; i < 4; ++i) {
+        const int e = tid + 256 * i;
+        const int jj = e & 31, cc = e >> 5;
+        const int j = j0 + jj, c = c0 + cc;
+        if (j < k && c < cr) gout[(size_t)tp * k * cr + (size_t)c * k + j] = tile[jj][cc];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+template <class T>
+void launch_theta(const GateDesc* d_desc, int n_gates, int max_tiles, hipStream_t stream) {
+  if (n_gates <= 0 || max_tiles <= 0) return;
+  hipLaunchKernelGGL(theta_kernel<T>, dim3(max_tiles, n_gates), dim3(256), 0, stream, d_desc);
+}
+
+template <class T>
+void launch_jacobi_init(const GateDesc* d_desc, int n_gates, int max_c, const LayerOut& out,
+                        hipStream_t stream) {
+  if (n_gates <= 0) return;
+  int blocks = (int)(((size_t)max_c * max_c + 255) / 256);
+  if (blocks > 256) blocks = 256;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(jacobi_init_kernel<T>, dim3(blocks, n_gates), dim3(256), 0, stream, d_desc,
+                     out);
+}
+
+template <class T>
+void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
+                         const LayerOut& out, double tol_scale, int inner_sweeps,
+                         hipStream_t stream) {
+  if (n_gates <= 0 || nbp < 2) return;
+  hipLaunchKernelGGL(jacobi_round_kernel<T>, dim3(nbp / 2, n_gates), dim3(256), 0, stream,
+                     d_desc, round, nbp, out, tol_scale, inner_sweeps);
+}
+
+void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
+                        double unit_roundoff, const LayerOut& out, hipStream_t stream) {
+  const int blocks = (n_gates + 255) / 256;
+  hipLaunchKernelGGL(sweep_check_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, stream,
+                     d_desc, n_gates, sweep, tol_factor, unit_roundoff, out);
+}
+
+template <class T>
+void launch_finalize(const GateDesc* d_desc, int n_gates, double cutoff, const LayerOut& out,
+                     hipStream_t stream) {
+  if (n_gates <= 0) return;
+  hipLaunchKernelGGL(finalize_kernel<T>, dim3(n_gates), dim3(256), 0, stream, d_desc, cutoff,
+                     out);
+}
+
+template <class T>
+void launch_writeback(const GateDesc* d_desc, int n_gates, const LayerOut& out,
+                      hipStream_t stream) {
+  if (n_gates <= 0) return;
+  hipLaunchKernelGGL(writeback_kernel<T>, dim3(64, n_gates, 2), dim3(256), 0, stream, d_desc,
+                     out);
+}
+
+template void launch_theta<float>(const GateDesc*, int, int, hipStream_t);
+template void launch_theta<double>(const GateDesc*, int, int, hipStream_t);
+template void launch_jacobi_init<float>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
+template void launch_jacobi_init<double>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
+template void launch_jacobi_round<float>(const GateDesc*, int, int, int, const LayerOut&, double,
+                                         int, hipStream_t);
+template void launch_jacobi_round<double>(const GateDesc*, int, int, int, const LayerOut&, double,
+                                          int, hipStream_t);
+template void launch_finalize<float>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
+template void launch_finalize<double>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
+template void launch_writeback<float>(const GateDesc*, int, const LayerOut&, hipStream_t);
+template void launch_writeback<double>(const GateDesc*, int, const LayerOut&, hipStream_t);
+
+}  // namespace ptebd

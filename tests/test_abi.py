@@ -1,0 +1,78 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry point,
+and rejects bad arguments before touching the device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2312_02667_amd import ptebd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ptebd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptebd_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ptebd.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(ptebd.EXPORTED)
+
+
+def test_version_string():
+    assert ptebd.lib().ptebd_version().decode().startswith("ptebd")
+
+
+def _create(n_states, n_sites, caps, d=2, precision=0):
+    lib = ptebd.lib()
+    ns = np.asarray(n_sites, np.int32)
+    cs = np.asarray(caps, np.int32)
+    h = ctypes.c_void_p()
+    code = lib.ptebd_mps_create(n_states, ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                cs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), d, precision,
+                                None, ctypes.byref(h))
+    return code, h
+
+
+@pytest.mark.parametrize("args", [
+    (1, [10], [32], 3, 0),      # d must be 2
+    (0, [10], [32], 2, 0),      # no states
+    (1, [1], [32], 2, 0),       # N < 2
+    (1, [10], [0], 2, 0),       # chi_cap < 1
+    (1, [10], [1024], 2, 0),    # chi_cap > 512
+    (1, [10], [32], 2, 7),      # unknown precision
+])
+def test_create_rejects_bad_arguments_before_device_work(args):
+    code, h = _create(*args)
+    assert code == ptebd.EINVAL
+    assert not h.value
+    assert ptebd.lib().ptebd_last_error().decode()
+
+
+def test_null_handle_calls_are_rejected():
+    lib = ptebd.lib()
+    out = ctypes.c_double()
+    assert lib.ptebd_norm(None, 0, ctypes.byref(out)) == ptebd.EINVAL
+    assert lib.ptebd_apply_layer(None, 0, None, None, None, 4, 1e-12, 0, 0, None) == ptebd.EINVAL
+    assert lib.ptebd_mps_destroy(None) == ptebd.OK
+
+
+def test_svd_batched_rejects_bad_arguments():
+    lib = ptebd.lib()
+    a = np.zeros(8)
+    s = np.zeros(2)
+    p = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ps = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.ptebd_svd_batched(0, 0, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
+    assert lib.ptebd_svd_batched(5, 1, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
+    a[0] = np.nan
+    assert lib.ptebd_svd_batched(0, 1, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
