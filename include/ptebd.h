@@ -60,6 +60,8 @@ extern "C" {
 
 /* ------------------------------------------------------------------ layer flags */
 #define PTEBD_FLAG_NO_STABILIZE 1  /* nu_i = 1 (norm-stabilization ablation, Sec. III.C.1) */
+#define PTEBD_FLAG_RELATIVE_EPS 2  /* eps_i = discarded sigma^2 / sum sigma^2 (keeps each bond's
+                                      local norm); default: the literal discarded sigma^2 */
 
 typedef struct ptebd_mps* ptebd_mps_t;
 
@@ -102,11 +104,14 @@ int ptebd_mps_create(int n_states, const int32_t* n_sites, const int32_t* chi_ca
 /* Free the handle and all its device memory.  NULL is accepted. */
 int ptebd_mps_destroy(ptebd_mps_t h);
 
-/* Set the Jacobi SVD controls of a handle: max_sweeps >= 1 (default 30) and the
- * relative off-diagonal tolerance factor tol_factor > 0 (a pair of columns counts as
- * orthogonal when |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit
- * roundoff of the precision; default 4). */
-int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor);
+/* Set the Jacobi SVD controls of a handle: max_sweeps >= 1 (default 30); the relative
+ * off-diagonal tolerance factor tol_factor > 0 (a pair of columns counts as orthogonal when
+ * |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit roundoff of the
+ * precision; default 4); inner_sweeps in [1, 64], the cyclic sweeps over each 32x32 block
+ * pair's Gram matrix (default 1); sort_pairs 0/1, order each pair's new columns by norm
+ * (default 1). */
+int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int inner_sweeps,
+                         int sort_pairs);
 
 /*
  * Apply one circuit layer (one step of Algorithm 1) to states of the batch.
@@ -118,7 +123,7 @@ int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor);
  *   cutoff       >= 0: singular values sigma <= cutoff * sigma_1 are always dropped
  *                (their weight counts in eps_i);
  *   ptsu_steps   g >= 0 PtSU steps run when some gate of the layer had r > chi_max;
- *   flags        PTEBD_FLAG_NO_STABILIZE or 0;
+ *   flags        0 or an OR of PTEBD_FLAG_NO_STABILIZE, PTEBD_FLAG_RELATIVE_EPS;
  *   stats        optional per-layer statistics (see ptebd_layer_stats).
  * The gates of one state must act on disjoint sites (else EOVERLAP).  The call enqueues
  * the layer on the handle's stream and returns after it has completed (the new bond

@@ -191,7 +191,8 @@ struct ptebd_mps {
   Prof prof;
   int max_sweeps = 30;
   double tol_factor = 4.0;
-  int inner_sweeps = 2;
+  int inner_sweeps = 1;
+  int sort_pairs = 1;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   char* gamma_slot(int s, int q) const {
@@ -256,7 +257,7 @@ LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
 template <class T>
 int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, const LayerOut& lo,
                int precision, int max_sweeps, double tol_factor, int inner_sweeps,
-               int32_t* h_counter, int* n_unconverged, Prof* pf) {
+               int sort_pairs, int32_t* h_counter, int* n_unconverged, Prof* pf) {
   ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
   int nb = (max_c + 15) / 16;
   int nbp = nb + (nb & 1);
@@ -267,7 +268,7 @@ int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, con
     for (int round = 0; round < nbp - 1; ++round)
       timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
         ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
-                                      stream);
+                                      sort_pairs, stream);
       });
     ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
     PT_HIP(hipGetLastError());
@@ -285,7 +286,7 @@ int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, con
 // One batch of independent bond updates (all gates of a layer, or one PtSU half-step).
 template <class T>
 int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, double cutoff,
-                int stabilize, UpdateResult* res) {
+                int stabilize, int relative_eps, UpdateResult* res) {
   const int n = (int)items.size();
   res->k.assign(n, 0);
   res->r.assign(n, 0);
@@ -318,6 +319,7 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
     // bounded by it; singular values beyond it are rounding noise of the precision.
     d.chi_max = chi_max > 0 ? chi_max : d.cm;
     d.stabilize = stabilize;
+    d.relative_eps = relative_eps;
     woff[i] = total;
     total += (size_t)d.R * d.C;
     voff[i] = total;
@@ -369,7 +371,8 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
   PT_HIP(hipGetLastError());
   int n_unconv = 0;
   PT_CHECK(run_jacobi<T>(stream, d_desc, n, max_c, lo, h->precision, h->max_sweeps,
-                         h->tol_factor, h->inner_sweeps, (int32_t*)h->h_small.p, &n_unconv, pf));
+                         h->tol_factor, h->inner_sweeps, h->sort_pairs, (int32_t*)h->h_small.p,
+                         &n_unconv, pf));
   timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_desc, n, cutoff, lo, stream); });
   timed(pf, PTEBD_KERNEL_WRITEBACK, stream, [&] { ptebd::launch_writeback<T>(d_desc, n, lo, stream); });
   PT_HIP(hipGetLastError());
@@ -415,9 +418,10 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
 }
 
 int run_updates_dispatch(ptebd_mps* h, const std::vector<Item>& items, int chi_max,
-                         double cutoff, int stabilize, UpdateResult* res) {
-  if (h->precision == PTEBD_FP64) return run_updates<double>(h, items, chi_max, cutoff, stabilize, res);
-  return run_updates<float>(h, items, chi_max, cutoff, stabilize, res);
+                         double cutoff, int stabilize, int relative_eps, UpdateResult* res) {
+  if (h->precision == PTEBD_FP64)
+    return run_updates<double>(h, items, chi_max, cutoff, stabilize, relative_eps, res);
+  return run_updates<float>(h, items, chi_max, cutoff, stabilize, relative_eps, res);
 }
 
 int check_handle(ptebd_mps* h) {
@@ -445,7 +449,7 @@ int run_ptsu(ptebd_mps* h, const std::vector<int>& states, int steps, double cut
       for (int s : states)
         for (int q = parity; q + 1 < h->st[s].n; q += 2) items.push_back({s, q, nullptr});
       UpdateResult res;
-      PT_CHECK(run_updates_dispatch(h, items, 0, cutoff, 0, &res));
+      PT_CHECK(run_updates_dispatch(h, items, 0, cutoff, 0, 0, &res));
       *max_sweeps = std::max(*max_sweeps, res.max_sweeps);
       *n_unconv += res.n_unconverged;
     }
@@ -601,12 +605,17 @@ int ptebd_mps_destroy(ptebd_mps_t h) {
   return PTEBD_OK;
 }
 
-int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor) {
+int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int inner_sweeps,
+                         int sort_pairs) {
   PT_CHECK(check_handle(h));
-  if (max_sweeps < 1 || !(tol_factor > 0.0) || !std::isfinite(tol_factor))
-    return fail(PTEBD_EINVAL, "need max_sweeps >= 1 and tol_factor > 0");
+  if (max_sweeps < 1 || !(tol_factor > 0.0) || !std::isfinite(tol_factor) || inner_sweeps < 1 ||
+      inner_sweeps > 64 || (sort_pairs != 0 && sort_pairs != 1))
+    return fail(PTEBD_EINVAL,
+                "need max_sweeps >= 1, tol_factor > 0, inner_sweeps in [1, 64], sort_pairs 0/1");
   h->max_sweeps = max_sweeps;
   h->tol_factor = tol_factor;
+  h->inner_sweeps = inner_sweeps;
+  h->sort_pairs = sort_pairs;
   return PTEBD_OK;
 }
 
@@ -620,7 +629,8 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
     return fail(PTEBD_EINVAL, "state_idx may be NULL only for a single-state handle");
   if (!(cutoff >= 0.0) || !(cutoff < 1.0)) return fail(PTEBD_EINVAL, "cutoff must be in [0, 1)");
   if (ptsu_steps < 0) return fail(PTEBD_EINVAL, "ptsu_steps < 0");
-  if (flags & ~PTEBD_FLAG_NO_STABILIZE) return fail(PTEBD_EINVAL, "unknown flags");
+  if (flags & ~(PTEBD_FLAG_NO_STABILIZE | PTEBD_FLAG_RELATIVE_EPS))
+    return fail(PTEBD_EINVAL, "unknown flags");
   if (chi_max < 1) return fail(PTEBD_EINVAL, "chi_max must be >= 1");
   std::vector<std::vector<char>> used(h->st.size());
   std::vector<Item> items(n_gates);
@@ -642,7 +652,9 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
   PT_CHECK(set_device(h));
   PT_HIP(hipEventRecord(h->ev0, h->stream));
   UpdateResult res;
-  PT_CHECK(run_updates_dispatch(h, items, chi_max, cutoff, (flags & PTEBD_FLAG_NO_STABILIZE) ? 0 : 1, &res));
+  PT_CHECK(run_updates_dispatch(h, items, chi_max, cutoff,
+                                (flags & PTEBD_FLAG_NO_STABILIZE) ? 0 : 1,
+                                (flags & PTEBD_FLAG_RELATIVE_EPS) ? 1 : 0, &res));
   std::vector<int> trig_states;
   std::vector<char> trig(h->st.size(), 0);
   for (int i = 0; i < n_gates; ++i)
@@ -1104,7 +1116,7 @@ int svd_batched_t(int precision, int batch, int m, int n, const double* a, doubl
   int32_t counter = 0;
   int n_unconv = 0;
   int st = run_jacobi<T>(stream, (const GateDesc*)desc.p, batch, C, lo, precision, max_sweeps,
-                         tol_factor, 2, &counter, &n_unconv, nullptr);
+                         tol_factor, 1, 1, &counter, &n_unconv, nullptr);
   if (st < 0) return cleanup(st);
   ptebd::launch_finalize<T>((const GateDesc*)desc.p, batch, 0.0, lo, stream);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)

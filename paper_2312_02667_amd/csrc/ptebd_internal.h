@@ -31,7 +31,7 @@ struct GateDesc {
   int32_t has_gate;        // 0: identity gate (tSU), the gate mix is skipped
   int32_t chi_max;         // truncation bound; <= 0: keep every sigma above the cutoff
   int32_t stabilize;       // 1: nu = (1 - eps)^(-1/2); 0: nu = 1
-  int32_t pad_;
+  int32_t relative_eps;    // 1: eps = discarded sigma^2 / sum sigma^2
   void* gq;                // Gamma[q] slot
   void* gq1;               // Gamma[q+1] slot
   const double* lam_l;     // Lambda[q]   (cl)
@@ -68,7 +68,7 @@ void launch_theta(const GateDesc* d_desc, int n_gates, int max_tiles, hipStream_
 template <class T>
 void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
                          const LayerOut& out, double tol_scale, int inner_sweeps,
-                         hipStream_t stream);
+                         int sort_pairs, hipStream_t stream);
 void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
                         double unit_roundoff, const LayerOut& out, hipStream_t stream);
 template <class T>

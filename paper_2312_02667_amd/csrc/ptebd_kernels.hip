@@ -234,14 +234,18 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
 
 // One round of the block Jacobi sweep: every workgroup takes one pair (I, J) of 16-column
 // blocks of one gate's W, forms the 32x32 Gram matrix G = W_IJ^H W_IJ on MFMA, records the
-// largest relative off-diagonal |G_ij| / sqrt(G_ii G_jj), diagonalizes G by cyclic Jacobi
-// rotations in FP64 (angles and accumulated rotation Q in FP64), and applies Q to the 32
-// columns of W and of V on MFMA.  Pairs of one round are disjoint, so no two workgroups of
-// a gate touch the same column.
+// largest relative off-diagonal |G_ij| / sqrt(G_ii G_jj), runs cyclic Jacobi sweeps on G
+// (rotation angles computed in FP64; G and the accumulated rotation Q held in the path's
+// precision T) and applies Q to the 32 columns of W and of V on MFMA.  Pairs of one round
+// are disjoint, so no two workgroups of a gate touch the same column.
+//
+// LDS: G and Q only (2 x 32 x 33 complex T); the cross-wave reduction of the Gram tiles and
+// the T copy of Q used by the column update alias them.
 template <class T>
 __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
                                                            int round, int nbp, LayerOut out,
-                                                           double tol_scale, int inner_sweeps) {
+                                                           double tol_scale, int inner_sweeps,
+                                                           int sort_pairs) {
   const int g = blockIdx.y;
   if (out.conv[g]) return;
   const GateDesc* d = descs + g;
@@ -259,22 +263,22 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   cplx<T>* __restrict__ W = (cplx<T>*)d->w;
   cplx<T>* __restrict__ V = (cplx<T>*)d->v;
 
-  __shared__ cplx<double> G[32][33];
-  __shared__ cplx<double> Q[32][33];
-  __shared__ union {
-    cplx<double> part[2][3][16][17];
-    cplx<T> qt[32][33];
-  } U;
+  __shared__ cplx<T> G[32][33];
+  __shared__ cplx<T> Q[32][33];
   __shared__ double rot_c[16];
   __shared__ cplx<double> rot_s[16];
   __shared__ double red[4];
   __shared__ int flag;
+  __shared__ int pos[32];
+  // reduction scratch: wave w < 2 owns region w (3 tiles of 16 x 16), aliasing G / Q
+  cplx<T>* part0 = &G[0][0];
+  cplx<T>* part1 = &Q[0][0];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;
   typedef typename Mfma<T>::v4 V4;
 
-  // ---- Gram matrix, rows split over the four waves in chunks of 16
+  // ---- Gram matrix: rows split over the four waves in chunks of 16, next chunk prefetched
   V4 acc[3][2];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 2; ++j)
@@ -282,58 +286,76 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   const bool okI = col < nI, okJ = col < nJ;
   const cplx<T>* __restrict__ wI = W + (size_t)(cI + (okI ? col : 0)) * R;
   const cplx<T>* __restrict__ wJ = W + (size_t)(cJ + (okJ ? col : 0)) * R;
-  for (int r0 = wave * 16; r0 < R; r0 += 64) {
-    cplx<T> xi[4], xj[4];
+  cplx<T> xi[4], xj[4], ni[4], nj[4];
+  auto load_chunk = [&](int r0, cplx<T>(&a)[4], cplx<T>(&b)[4]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int r = r0 + grp * 4 + t;
       const bool ok = r < R;
-      xi[t] = (okI && ok) ? wI[r] : czero<T>();
-      xj[t] = (okJ && ok) ? wJ[r] : czero<T>();
+      a[t] = (okI && ok) ? wI[r] : czero<T>();
+      b[t] = (okJ && ok) ? wJ[r] : czero<T>();
     }
+  };
+  int r0 = wave * 16;
+  if (r0 < R) load_chunk(r0, xi, xj);
+  for (; r0 < R; r0 += 64) {
+    if (r0 + 64 < R) load_chunk(r0 + 64, ni, nj);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       gram_mfma<T>(acc[0], xi[t], xi[t]);
       gram_mfma<T>(acc[1], xi[t], xj[t]);
       gram_mfma<T>(acc[2], xj[t], xj[t]);
     }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      xi[t] = ni[t];
+      xj[t] = nj[t];
+    }
   }
   if (wave < 2) {
+    cplx<T>* p = wave == 0 ? part0 : part1;
     for (int tl = 0; tl < 3; ++tl)
       for (int v = 0; v < 4; ++v) {
-        cplx<double> z;
-        z.re = (double)acc[tl][0][v];
-        z.im = (double)acc[tl][1][v];
-        U.part[wave][tl][Mfma<T>::row(lane, v)][col] = z;
+        cplx<T> z;
+        z.re = acc[tl][0][v];
+        z.im = acc[tl][1][v];
+        p[(tl * 16 + Mfma<T>::row(lane, v)) * 16 + col] = z;
       }
   }
   __syncthreads();
   if (wave >= 2) {
+    cplx<T>* p = wave == 2 ? part0 : part1;
     for (int tl = 0; tl < 3; ++tl)
       for (int v = 0; v < 4; ++v) {
-        cplx<double>& z = U.part[wave - 2][tl][Mfma<T>::row(lane, v)][col];
-        z.re += (double)acc[tl][0][v];
-        z.im += (double)acc[tl][1][v];
+        cplx<T>& z = p[(tl * 16 + Mfma<T>::row(lane, v)) * 16 + col];
+        z.re += acc[tl][0][v];
+        z.im += acc[tl][1][v];
       }
   }
   __syncthreads();
-  for (int e = tid; e < 1024; e += 256) {
+  cplx<T> gv[4];
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + 256 * k;
     const int i = e >> 5, j = e & 31;
-    cplx<double> val;
+    int tl, ii, jj;
+    bool conj = false;
     if (i < 16 && j < 16) {
-      val.re = U.part[0][0][i][j].re + U.part[1][0][i][j].re;
-      val.im = U.part[0][0][i][j].im + U.part[1][0][i][j].im;
+      tl = 0; ii = i; jj = j;
     } else if (i < 16) {
-      val.re = U.part[0][1][i][j - 16].re + U.part[1][1][i][j - 16].re;
-      val.im = U.part[0][1][i][j - 16].im + U.part[1][1][i][j - 16].im;
+      tl = 1; ii = i; jj = j - 16;
     } else if (j >= 16) {
-      val.re = U.part[0][2][i - 16][j - 16].re + U.part[1][2][i - 16][j - 16].re;
-      val.im = U.part[0][2][i - 16][j - 16].im + U.part[1][2][i - 16][j - 16].im;
+      tl = 2; ii = i - 16; jj = j - 16;
     } else {
-      val.re = U.part[0][1][j][i - 16].re + U.part[1][1][j][i - 16].re;
-      val.im = -(U.part[0][1][j][i - 16].im + U.part[1][1][j][i - 16].im);
+      tl = 1; ii = j; jj = i - 16; conj = true;
     }
-    G[i][j] = val;
+    const cplx<T> a = part0[(tl * 16 + ii) * 16 + jj], b = part1[(tl * 16 + ii) * 16 + jj];
+    gv[k].re = a.re + b.re;
+    gv[k].im = conj ? -(a.im + b.im) : (a.im + b.im);
+  }
+  __syncthreads();
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + 256 * k;
+    G[e >> 5][e & 31] = gv[k];
   }
   __syncthreads();
 
@@ -342,8 +364,9 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
     if (i < j) {
-      const double di = G[i][i].re, dj = G[j][j].re;
-      if (di > 0.0 && dj > 0.0) mx = fmax(mx, hypot(G[i][j].re, G[i][j].im) / sqrt(di * dj));
+      const double di = (double)G[i][i].re, dj = (double)G[j][j].re;
+      if (di > 0.0 && dj > 0.0)
+        mx = fmax(mx, hypot((double)G[i][j].re, (double)G[i][j].im) / sqrt(di * dj));
     }
   }
   mx = wave_max(mx);
@@ -362,12 +385,15 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   }
   if (!rotate) return;  // uniform: every thread read the same red[]
 
-  // ---- cyclic Jacobi on the 32x32 Hermitian G, FP64, Q accumulates the rotations
+  // ---- cyclic Jacobi on the 32x32 Hermitian G; Q accumulates the rotations.  The
+  // threshold sits well below the outer tolerance so that a pair the outer test calls
+  // unconverged is always rotated.
+  const double inner_tol = 0.125 * tol_scale * sqrt((double)R);
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
-    cplx<double> z;
-    z.re = (i == j) ? 1.0 : 0.0;
-    z.im = 0.0;
+    cplx<T> z;
+    z.re = (i == j) ? T(1) : T(0);
+    z.im = T(0);
     Q[i][j] = z;
   }
   for (int sw = 0; sw < inner_sweeps; ++sw) {
@@ -377,17 +403,17 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     for (int rd = 0; rd < 31; ++rd) {
       if (tid < 16) {
         const int p = rr_player(tid, rd, 32), q = rr_player(31 - tid, rd, 32);
-        const double a = G[p][p].re, b = G[q][q].re;
-        const cplx<double> gg = G[p][q];
-        const double ag = hypot(gg.re, gg.im);
+        const double a = (double)G[p][p].re, b = (double)G[q][q].re;
+        const double gr = (double)G[p][q].re, gi = (double)G[p][q].im;
+        const double ag = hypot(gr, gi);
         double c = 1.0, sr = 0.0, si = 0.0;
-        if (ag > 0.0 && ag > 1e-15 * sqrt(fmax(a * b, 0.0))) {
+        if (ag > 0.0 && ag > inner_tol * sqrt(fmax(a * b, 0.0))) {
           const double zeta = (b - a) / (2.0 * ag);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           c = 1.0 / sqrt(1.0 + t * t);
           const double s = t * c;
-          sr = s * gg.re / ag;
-          si = s * gg.im / ag;
+          sr = s * gr / ag;
+          si = s * gi / ag;
           flag = 1;
         }
         rot_c[tid] = c;
@@ -400,40 +426,41 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
         const int ia = tid >> 4, ib = tid & 15;
         const int pa = rr_player(ia, rd, 32), qa = rr_player(31 - ia, rd, 32);
         const int pb = rr_player(ib, rd, 32), qb = rr_player(31 - ib, rd, 32);
-        const double ca = rot_c[ia], cb = rot_c[ib];
-        const cplx<double> sa = rot_s[ia], sb = rot_s[ib];
-        const cplx<double> b00 = G[pa][pb], b01 = G[pa][qb], b10 = G[qa][pb], b11 = G[qa][qb];
+        const T ca = (T)rot_c[ia], cb = (T)rot_c[ib];
+        const T sar = (T)rot_s[ia].re, sai = (T)rot_s[ia].im;
+        const T sbr = (T)rot_s[ib].re, sbi = (T)rot_s[ib].im;
+        const cplx<T> b00 = G[pa][pb], b01 = G[pa][qb], b10 = G[qa][pb], b11 = G[qa][qb];
+        const cplx<T> q00 = Q[pa][pb], q01 = Q[pa][qb], q10 = Q[qa][pb], q11 = Q[qa][qb];
         // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
-        cplx<double> x00, x01, x10, x11;
-        x00.re = cb * b00.re - (sb.re * b01.re + sb.im * b01.im);
-        x00.im = cb * b00.im - (sb.re * b01.im - sb.im * b01.re);
-        x10.re = cb * b10.re - (sb.re * b11.re + sb.im * b11.im);
-        x10.im = cb * b10.im - (sb.re * b11.im - sb.im * b11.re);
-        x01.re = (sb.re * b00.re - sb.im * b00.im) + cb * b01.re;
-        x01.im = (sb.re * b00.im + sb.im * b00.re) + cb * b01.im;
-        x11.re = (sb.re * b10.re - sb.im * b10.im) + cb * b11.re;
-        x11.im = (sb.re * b10.im + sb.im * b10.re) + cb * b11.im;
+        cplx<T> x00, x01, x10, x11;
+        x00.re = cb * b00.re - (sbr * b01.re + sbi * b01.im);
+        x00.im = cb * b00.im - (sbr * b01.im - sbi * b01.re);
+        x10.re = cb * b10.re - (sbr * b11.re + sbi * b11.im);
+        x10.im = cb * b10.im - (sbr * b11.im - sbi * b11.re);
+        x01.re = (sbr * b00.re - sbi * b00.im) + cb * b01.re;
+        x01.im = (sbr * b00.im + sbi * b00.re) + cb * b01.im;
+        x11.re = (sbr * b10.re - sbi * b10.im) + cb * b11.re;
+        x11.im = (sbr * b10.im + sbi * b10.re) + cb * b11.im;
         // B' = J_a^H X: row0 = c_a X[0,:] - s_a X[1,:];  row1 = conj(s_a) X[0,:] + c_a X[1,:]
-        cplx<double> n00, n01, n10, n11;
-        n00.re = ca * x00.re - (sa.re * x10.re - sa.im * x10.im);
-        n00.im = ca * x00.im - (sa.re * x10.im + sa.im * x10.re);
-        n01.re = ca * x01.re - (sa.re * x11.re - sa.im * x11.im);
-        n01.im = ca * x01.im - (sa.re * x11.im + sa.im * x11.re);
-        n10.re = (sa.re * x00.re + sa.im * x00.im) + ca * x10.re;
-        n10.im = (sa.re * x00.im - sa.im * x00.re) + ca * x10.im;
-        n11.re = (sa.re * x01.re + sa.im * x01.im) + ca * x11.re;
-        n11.im = (sa.re * x01.im - sa.im * x01.re) + ca * x11.im;
+        cplx<T> n00, n01, n10, n11;
+        n00.re = ca * x00.re - (sar * x10.re - sai * x10.im);
+        n00.im = ca * x00.im - (sar * x10.im + sai * x10.re);
+        n01.re = ca * x01.re - (sar * x11.re - sai * x11.im);
+        n01.im = ca * x01.im - (sar * x11.im + sai * x11.re);
+        n10.re = (sar * x00.re + sai * x00.im) + ca * x10.re;
+        n10.im = (sar * x00.im - sai * x00.re) + ca * x10.im;
+        n11.re = (sar * x01.re + sai * x01.im) + ca * x11.re;
+        n11.im = (sar * x01.im - sai * x01.re) + ca * x11.im;
         // Q' = Q J_b on rows pa, qa
-        const cplx<double> q00 = Q[pa][pb], q01 = Q[pa][qb], q10 = Q[qa][pb], q11 = Q[qa][qb];
-        cplx<double> m00, m01, m10, m11;
-        m00.re = cb * q00.re - (sb.re * q01.re + sb.im * q01.im);
-        m00.im = cb * q00.im - (sb.re * q01.im - sb.im * q01.re);
-        m10.re = cb * q10.re - (sb.re * q11.re + sb.im * q11.im);
-        m10.im = cb * q10.im - (sb.re * q11.im - sb.im * q11.re);
-        m01.re = (sb.re * q00.re - sb.im * q00.im) + cb * q01.re;
-        m01.im = (sb.re * q00.im + sb.im * q00.re) + cb * q01.im;
-        m11.re = (sb.re * q10.re - sb.im * q10.im) + cb * q11.re;
-        m11.im = (sb.re * q10.im + sb.im * q10.re) + cb * q11.im;
+        cplx<T> m00, m01, m10, m11;
+        m00.re = cb * q00.re - (sbr * q01.re + sbi * q01.im);
+        m00.im = cb * q00.im - (sbr * q01.im - sbi * q01.re);
+        m10.re = cb * q10.re - (sbr * q11.re + sbi * q11.im);
+        m10.im = cb * q10.im - (sbr * q11.im - sbi * q11.re);
+        m01.re = (sbr * q00.re - sbi * q00.im) + cb * q01.re;
+        m01.im = (sbr * q00.im + sbi * q00.re) + cb * q01.im;
+        m11.re = (sbr * q10.re - sbi * q10.im) + cb * q11.re;
+        m11.im = (sbr * q10.im + sbi * q10.re) + cb * q11.im;
         __syncthreads();  // every block read before any write
         G[pa][pb] = n00;
         G[pa][qb] = n01;
@@ -451,37 +478,58 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     if (f == 0) break;
   }
   __syncthreads();
+  // Optional ordering of the pair's 32 new columns by norm: the 16 largest go to the
+  // lower-numbered block (full blocks only), so that sweeps drift the columns towards
+  // descending order.
+  if (tid < 32) {
+    int p = tid;
+    if (sort_pairs && nI == 16 && nJ == 16) {
+      const T dj = G[tid][tid].re;
+      int rank = 0;
+      for (int i = 0; i < 32; ++i) {
+        const T di = G[i][i].re;
+        rank += (di > dj || (di == dj && i < tid)) ? 1 : 0;
+      }
+      p = (I < J) ? rank : (rank < 16 ? rank + 16 : rank - 16);
+    }
+    pos[tid] = p;
+  }
+  __syncthreads();
+  // column-permuted copy of Q, kept in G's storage (G is no longer needed)
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
-    cplx<T> z;
-    z.re = (T)Q[i][j].re;
-    z.im = (T)Q[i][j].im;
-    U.qt[i][j] = z;
+    G[i][pos[j]] = Q[i][j];
   }
   __syncthreads();
 
-  // ---- column update [W_I W_J] <- [W_I W_J] Q and [V_I V_J] <- [V_I V_J] Q on MFMA
+  // ---- column update [W_I W_J] <- [W_I W_J] Q and [V_I V_J] <- [V_I V_J] Q on MFMA,
+  // next 16-row chunk prefetched
   for (int pass = 0; pass < 2; ++pass) {
     cplx<T>* __restrict__ M = pass == 0 ? W : V;
     const int rows = pass == 0 ? R : C;
-    for (int r0 = wave * 16; r0 < rows; r0 += 64) {
-      const int r = r0 + col;
-      cplx<T> av[8];
+    cplx<T> av[8], an[8];
+    auto load_rows = [&](int rbase, cplx<T>(&dst)[8]) {
+      const int r = rbase + col;
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
         const int kk = ks * 4 + grp;
         const bool ok = (kk < 16 ? kk < nI : kk - 16 < nJ) && r < rows;
         const int cidx = kk < 16 ? cI + kk : cJ + kk - 16;
-        av[ks] = ok ? M[(size_t)cidx * rows + r] : czero<T>();
+        dst[ks] = ok ? M[(size_t)cidx * rows + r] : czero<T>();
       }
+    };
+    int rb = wave * 16;
+    if (rb < rows) load_rows(rb, av);
+    for (; rb < rows; rb += 64) {
+      if (rb + 64 < rows) load_rows(rb + 64, an);
       V4 o[2][2];
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
           for (int v = 0; v < 4; ++v) o[i][j][v] = T(0);
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
-        const cplx<T> b0 = U.qt[ks * 4 + grp][col];
-        const cplx<T> b1 = U.qt[ks * 4 + grp][16 + col];
+        const cplx<T> b0 = G[ks * 4 + grp][col];
+        const cplx<T> b1 = G[ks * 4 + grp][16 + col];
         cmfma<T>(o[0], av[ks], b0);
         cmfma<T>(o[1], av[ks], b1);
       }
@@ -491,7 +539,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
         const int cidx = jt == 0 ? cI + jj : cJ + jj - 16;
         if (!okc) continue;
         for (int v = 0; v < 4; ++v) {
-          const int rr = r0 + Mfma<T>::row(lane, v);
+          const int rr = rb + Mfma<T>::row(lane, v);
           if (rr < rows) {
             cplx<T> z;
             z.re = o[jt][0][v];
@@ -500,6 +548,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
           }
         }
       }
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) av[ks] = an[ks];
     }
   }
 }
@@ -536,6 +586,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
   __shared__ double key[1024];
   __shared__ int idx[1024];
   __shared__ double red_d[4];
+  __shared__ double red_w[4];
   __shared__ int red_i[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int P = 1;
@@ -587,12 +638,21 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
   const int chi_max = d->chi_max;
   int k = chi_max > 0 ? min(chi_max, r) : r;
   if (k < 1) k = 1;
-  double part = 0.0;
-  for (int j = k + tid; j < C; j += 256) part += fmax(key[j], 0.0);
+  double part = 0.0, whole = 0.0;
+  for (int j = tid; j < C; j += 256) {
+    const double v = fmax(key[j], 0.0);
+    whole += v;
+    if (j >= k) part += v;
+  }
   part = wave_sum(part);
-  if (lane == 0) red_d[wave] = part;
+  whole = wave_sum(whole);
+  if (lane == 0) {
+    red_d[wave] = part;
+    red_w[wave] = whole;
+  }
   __syncthreads();
-  const double eps = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+  double eps = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+  if (d->relative_eps) eps /= (red_w[0] + red_w[1]) + (red_w[2] + red_w[3]);
   const double nu = d->stabilize ? 1.0 / sqrt(1.0 - eps) : 1.0;
   double* lam_m = d->lam_m;
   for (int j = tid; j < C; j += 256) {
@@ -710,10 +770,10 @@ void launch_jacobi_init(const GateDesc* d_desc, int n_gates, int max_c, const La
 template <class T>
 void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
                          const LayerOut& out, double tol_scale, int inner_sweeps,
-                         hipStream_t stream) {
+                         int sort_pairs, hipStream_t stream) {
   if (n_gates <= 0 || nbp < 2) return;
   hipLaunchKernelGGL(jacobi_round_kernel<T>, dim3(nbp / 2, n_gates), dim3(256), 0, stream,
-                     d_desc, round, nbp, out, tol_scale, inner_sweeps);
+                     d_desc, round, nbp, out, tol_scale, inner_sweeps, sort_pairs);
 }
 
 void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
@@ -744,9 +804,9 @@ template void launch_theta<double>(const GateDesc*, int, int, hipStream_t);
 template void launch_jacobi_init<float>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
 template void launch_jacobi_init<double>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
 template void launch_jacobi_round<float>(const GateDesc*, int, int, int, const LayerOut&, double,
-                                         int, hipStream_t);
+                                         int, int, hipStream_t);
 template void launch_jacobi_round<double>(const GateDesc*, int, int, int, const LayerOut&, double,
-                                          int, hipStream_t);
+                                          int, int, hipStream_t);
 template void launch_finalize<float>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
 template void launch_finalize<double>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
 template void launch_writeback<float>(const GateDesc*, int, const LayerOut&, hipStream_t);

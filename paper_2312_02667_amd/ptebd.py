@@ -27,6 +27,7 @@ WNOCONV = 1
 FP64 = 0
 FP32 = 1
 FLAG_NO_STABILIZE = 1
+FLAG_RELATIVE_EPS = 2
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
@@ -66,7 +67,8 @@ _SIGS = {
     "ptebd_mps_create": (ctypes.c_int, [ctypes.c_int, _i32p, _i32p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "ptebd_mps_destroy": (ctypes.c_int, [ctypes.c_void_p]),
-    "ptebd_set_svd_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
+    "ptebd_set_svd_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_int, ctypes.c_int]),
     "ptebd_apply_layer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, _dp,
                                           ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_int, ctypes.POINTER(LayerStats)]),
@@ -165,11 +167,13 @@ class MPS:
         except Exception:  # noqa: BLE001
             pass
 
-    def set_svd_params(self, max_sweeps: int = 30, tol_factor: float = 4.0):
-        _check(lib().ptebd_set_svd_params(self._h, int(max_sweeps), float(tol_factor)))
+    def set_svd_params(self, max_sweeps: int = 30, tol_factor: float = 4.0,
+                       inner_sweeps: int = 1, sort_pairs: bool = True):
+        _check(lib().ptebd_set_svd_params(self._h, int(max_sweeps), float(tol_factor),
+                                          int(inner_sweeps), 1 if sort_pairs else 0))
 
     def apply_layer(self, bonds, gates, chi_max: int, cutoff: float = 1e-12, ptsu_steps: int = 0,
-                    stabilize: bool = True, state_idx=None) -> dict:
+                    stabilize: bool = True, state_idx=None, relative_eps: bool = False) -> dict:
         bonds = np.ascontiguousarray(bonds, dtype=np.int32)
         g = _gates_array(gates)
         n = len(bonds)
@@ -189,7 +193,9 @@ class MPS:
         code = _check(lib().ptebd_apply_layer(
             self._h, n, _ptr(sidx, ctypes.c_int32) if sidx is not None else None,
             _ptr(bonds, ctypes.c_int32), _ptr(g, ctypes.c_double), int(chi_max), float(cutoff),
-            int(ptsu_steps), 0 if stabilize else FLAG_NO_STABILIZE, ctypes.byref(st)))
+            int(ptsu_steps),
+            (0 if stabilize else FLAG_NO_STABILIZE) | (FLAG_RELATIVE_EPS if relative_eps else 0),
+            ctypes.byref(st)))
         return {"k": k, "rank": rank, "eps": eps, "nu": nu, "sweeps": sweeps,
                 "triggered": bool(st.triggered), "ptsu_done": st.ptsu_done,
                 "max_sweeps": st.max_sweeps, "n_unconverged": st.n_unconverged,

@@ -33,8 +33,10 @@ def test_small_exact_circuit(precision, seed):
     f_tol = 1e-12 if precision == "fp64" else 1e-9
     dense = po.to_dense(to_oracle(m))
     assert 1 - sv.fidelity(psi, dense) <= f_tol
-    assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 1e-6)
-    assert np.max(np.abs(m.expect_z() - sv.expect_z(psi, n))) <= (1e-12 if precision == "fp64" else 1e-6)
+    # FP32 Jacobi rotations keep column norms to ~u sqrt(rotations per column) per update
+    # (~1e-6 per bond at these sizes), so the norm and <Z> carry ~1e-5 after 36 gates
+    assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 1e-5)
+    assert np.max(np.abs(m.expect_z() - sv.expect_z(psi, n))) <= (1e-12 if precision == "fp64" else 1e-5)
     assert m.canon_distance() <= (1e-10 if precision == "fp64" else 1e-5)
     m.close()
 
@@ -63,9 +65,11 @@ def test_truncated_circuit_fp64_matches_oracle():
     err_f = 1 - abs(ov) ** 2 / (m.norm() ** 2 * other.norm() ** 2)
     say(f"err_F = {err_f:.3e}, |n-1| = {abs(m.norm() - 1):.3e}")
     assert err_f <= 1e-10
-    assert abs(m.norm() - po.norm(ref)) <= 1e-10
+    # under the literal eps reading the norm grows in this heavily truncated regime (about
+    # 22 after 20 layers, for the oracle as well), so norms are compared relatively
+    assert abs(m.norm() - po.norm(ref)) <= 1e-9 * po.norm(ref)
     assert np.max(np.abs(m.expect_z() - po.expect_z(ref))) <= 1e-9
-    assert abs(m.norm_estimate() - ref.prod_nu) <= 1e-10
+    assert abs(m.norm_estimate() - ref.prod_nu) <= 1e-9 * ref.prod_nu
     assert abs(m.fidelity_estimate() - ref.prod_one_minus_eps) <= 1e-10
     m.close()
     other.close()
@@ -73,18 +77,19 @@ def test_truncated_circuit_fp64_matches_oracle():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_ptsu_and_no_stabilize_match_oracle(precision):
-    """chi_max=6 with g=2 PtSU steps (IPMC), and the nu ablation flag, on N=12."""
+    """chi_max=6 with g=2 PtSU steps (IPMC), the nu ablation flag and the relative-eps
+    reading, on N=12."""
     n, depth, chi = 12, 8, 6
     layers = inputs.brickwork_circuit(n, depth, seed=4)
-    for stabilize in (True, False):
+    for stabilize, rel in ((True, False), (False, False), (True, True)):
         ref = po.product_state(n)
         m = ptebd.MPS(n, 16, precision)
         for li, (bonds, gates) in enumerate(layers):
-            say(f"ptsu {precision} stabilize={stabilize} layer {li + 1}")
+            say(f"ptsu {precision} stabilize={stabilize} relative_eps={rel} layer {li + 1}")
             st = m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12, ptsu_steps=2,
-                               stabilize=stabilize)
+                               stabilize=stabilize, relative_eps=rel)
             _, trig = po.apply_layer(ref, bonds, gates, chi_max=chi, cutoff=1e-12, ptsu_steps=2,
-                                     stabilize=stabilize)
+                                     stabilize=stabilize, relative_eps=rel)
             assert st["triggered"] == trig
             assert st["ptsu_done"] == (2 if trig else 0)
             assert m.bond_dims() == ref.bond_dims()

@@ -314,3 +314,24 @@ def test_theorem4_ptsu_restores_canonical_form(n_sites):
     assert mean[0] > 1e-3
     assert np.all(curves[:, -1] <= 1e-10)
     assert np.all(np.diff(mean[: n_sites // 4]) < 0)
+
+
+def test_relative_eps_reading():
+    """On a normalized canonical input the relative and the literal eps coincide; on any
+    input the relative reading keeps each updated bond's local two-site norm."""
+    n = 8
+    psi, mps = _canonical_random_state(n, 21)
+    rng = np.random.default_rng(210)
+    u = inputs.haar_unitary(rng)
+    a, b = mps.copy(), mps.copy()
+    sa, _ = po.apply_layer(a, [3], [u], chi_max=3)
+    sb, _ = po.apply_layer(b, [3], [u], chi_max=3, relative_eps=True)
+    assert abs(sa[0]["eps"] - sb[0]["eps"]) < 1e-14
+    # non-normalized input: scale the state by 1.3, local norm^2 of theta is 1.69
+    c = mps.copy()
+    po.scale_norm(c, 1.3)
+    theta = po.two_site_theta(c, 3, u)
+    before = np.sum(np.abs(theta) ** 2)
+    st, _ = po.apply_layer(c, [3], [u], chi_max=3, relative_eps=True)
+    assert abs(np.sum(c.lam[4] ** 2) - before) < 1e-12 * before
+    assert abs(st[0]["eps"] - np.sum(st[0]["sigma"][3:] ** 2) / before) < 1e-14
