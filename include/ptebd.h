@@ -108,8 +108,8 @@ int ptebd_mps_destroy(ptebd_mps_t h);
  * off-diagonal tolerance factor tol_factor > 0 (a pair of columns counts as orthogonal when
  * |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit roundoff of the
  * precision; default 4); inner_sweeps in [1, 64], the cyclic sweeps over each 32x32 block
- * pair's Gram matrix (default 1); sort_pairs 0/1, order each pair's new columns by norm
- * (default 1). */
+ * pair's Gram matrix (default 2 for FP32, 1 for FP64); sort_pairs 0/1, order each pair's
+ * new columns by norm (default 1). */
 int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int inner_sweeps,
                          int sort_pairs);
 

@@ -168,7 +168,9 @@ class MPS:
             pass
 
     def set_svd_params(self, max_sweeps: int = 30, tol_factor: float = 4.0,
-                       inner_sweeps: int = 1, sort_pairs: bool = True):
+                       inner_sweeps: int | None = None, sort_pairs: bool = True):
+        if inner_sweeps is None:
+            inner_sweeps = 1 if self.precision == "fp64" else 2
         _check(lib().ptebd_set_svd_params(self._h, int(max_sweeps), float(tol_factor),
                                           int(inner_sweeps), 1 if sort_pairs else 0))
 
