@@ -77,6 +77,51 @@ __device__ inline int rr_player(int slot, int round, int nplayers) {
   return slot == 0 ? 0 : 1 + ((slot - 1 + round) % (nplayers - 1));
 }
 
+// The same tournament for 32 players and round < 31, without an integer division.
+__device__ inline int rr32(int slot, int round) {
+  int x = slot - 1 + round;
+  x -= (x >= 31) ? 31 : 0;
+  return slot == 0 ? 0 : 1 + x;
+}
+
+// FP64 reciprocal square root and reciprocal: hardware estimate refined by two Newton
+// steps (each doubles the number of correct bits), for positive finite arguments.
+__device__ inline double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+__device__ inline double rcp_f64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * (2.0 - x * y);
+  y = y * (2.0 - x * y);
+  return y;
+}
+
+// Jacobi rotation of the Hermitian 2x2 block [[a, g], [conj(g), b]] in FP64 (the symmetric
+// Schur step with the phase of g factored out): J = [[c, s], [-conj(s), c]] with
+// zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
+// s = t c g/|g|; J^H [[a, g], [conj g, b]] J is diagonal.  Identity when
+// |g| <= thr * sqrt(a b) or g = 0.  Returns whether a rotation is applied.
+__device__ inline bool jacobi_rotation(double a, double b, double gr, double gi, double thr,
+                                       double& c, double& sr, double& si) {
+  const double g2 = gr * gr + gi * gi;
+  c = 1.0;
+  sr = 0.0;
+  si = 0.0;
+  if (!(g2 > 0.0) || g2 <= thr * thr * fmax(a * b, 0.0)) return false;
+  const double rg = rsqrt_f64(g2);  // 1 / |g|
+  const double zeta = 0.5 * (b - a) * rg;
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_f64(fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = rsqrt_f64(1.0 + t * t);
+  const double sc = t * c * rg;
+  sr = sc * gr;
+  si = sc * gi;
+  return true;
+}
+
 // ---------------------------------------------------------------- theta
 // One workgroup computes a 32 (a) x 32 (c) tile of the four products
 // M_st = A_s B_t, A_s = diag(Lambda[q]) Gamma[q]_s diag(Lambda[q+1]) (chi_q x chi_{q+1}),
@@ -264,9 +309,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   cplx<T>* __restrict__ V = (cplx<T>*)d->v;
 
   __shared__ cplx<T> G[32][33];
+  __shared__ cplx<T> G2[32][33];
   __shared__ cplx<T> Q[32][33];
-  __shared__ double rot_c[16];
-  __shared__ cplx<double> rot_s[16];
   __shared__ double red[4];
   __shared__ int flag;
   __shared__ int pos[32];
@@ -396,82 +440,75 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     z.im = T(0);
     Q[i][j] = z;
   }
+  // Each round pairs the 32 indices by the round-robin tournament; every thread owns one
+  // 2x2 block (row pair ia, column pair ib) of G and of Q.  Every wave computes the 16
+  // rotations of the round itself (lanes 0..15, FP64) and hands them to its lanes by
+  // shuffles, so a round needs a single barrier: G is double-buffered, and each Q block is
+  // read and written only by its owner.
+  cplx<T>(*Gc)[33] = G;
+  cplx<T>(*Gn)[33] = G2;
+  const int ia = tid >> 4, ib = tid & 15;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     __syncthreads();
     if (tid == 0) flag = 0;
     __syncthreads();
     for (int rd = 0; rd < 31; ++rd) {
-      if (tid < 16) {
-        const int p = rr_player(tid, rd, 32), q = rr_player(31 - tid, rd, 32);
-        const double a = (double)G[p][p].re, b = (double)G[q][q].re;
-        const double gr = (double)G[p][q].re, gi = (double)G[p][q].im;
-        const double ag = hypot(gr, gi);
-        double c = 1.0, sr = 0.0, si = 0.0;
-        if (ag > 0.0 && ag > inner_tol * sqrt(fmax(a * b, 0.0))) {
-          const double zeta = (b - a) / (2.0 * ag);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          const double s = t * c;
-          sr = s * gr / ag;
-          si = s * gi / ag;
-          flag = 1;
-        }
-        rot_c[tid] = c;
-        rot_s[tid].re = sr;
-        rot_s[tid].im = si;
+      double c = 1.0, sr = 0.0, si = 0.0;
+      if (lane < 16) {
+        const int p = rr32(lane, rd), q = rr32(31 - lane, rd);
+        const bool did = jacobi_rotation((double)Gc[p][p].re, (double)Gc[q][q].re,
+                                         (double)Gc[p][q].re, (double)Gc[p][q].im, inner_tol, c,
+                                         sr, si);
+        if (did && wave == 0) flag = 1;
       }
+      const T ca = (T)__shfl(c, ia), sar = (T)__shfl(sr, ia), sai = (T)__shfl(si, ia);
+      const T cb = (T)__shfl(c, ib), sbr = (T)__shfl(sr, ib), sbi = (T)__shfl(si, ib);
+      const int pa = rr32(ia, rd), qa = rr32(31 - ia, rd);
+      const int pb = rr32(ib, rd), qb = rr32(31 - ib, rd);
+      const cplx<T> b00 = Gc[pa][pb], b01 = Gc[pa][qb], b10 = Gc[qa][pb], b11 = Gc[qa][qb];
+      const cplx<T> q00 = Q[pa][pb], q01 = Q[pa][qb], q10 = Q[qa][pb], q11 = Q[qa][qb];
+      // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
+      cplx<T> x00, x01, x10, x11;
+      x00.re = cb * b00.re - (sbr * b01.re + sbi * b01.im);
+      x00.im = cb * b00.im - (sbr * b01.im - sbi * b01.re);
+      x10.re = cb * b10.re - (sbr * b11.re + sbi * b11.im);
+      x10.im = cb * b10.im - (sbr * b11.im - sbi * b11.re);
+      x01.re = (sbr * b00.re - sbi * b00.im) + cb * b01.re;
+      x01.im = (sbr * b00.im + sbi * b00.re) + cb * b01.im;
+      x11.re = (sbr * b10.re - sbi * b10.im) + cb * b11.re;
+      x11.im = (sbr * b10.im + sbi * b10.re) + cb * b11.im;
+      // B' = J_a^H X: row0 = c_a X[0,:] - s_a X[1,:];  row1 = conj(s_a) X[0,:] + c_a X[1,:]
+      cplx<T> n00, n01, n10, n11;
+      n00.re = ca * x00.re - (sar * x10.re - sai * x10.im);
+      n00.im = ca * x00.im - (sar * x10.im + sai * x10.re);
+      n01.re = ca * x01.re - (sar * x11.re - sai * x11.im);
+      n01.im = ca * x01.im - (sar * x11.im + sai * x11.re);
+      n10.re = (sar * x00.re + sai * x00.im) + ca * x10.re;
+      n10.im = (sar * x00.im - sai * x00.re) + ca * x10.im;
+      n11.re = (sar * x01.re + sai * x01.im) + ca * x11.re;
+      n11.im = (sar * x01.im - sai * x01.re) + ca * x11.im;
+      // Q' = Q J_b on rows pa, qa
+      cplx<T> m00, m01, m10, m11;
+      m00.re = cb * q00.re - (sbr * q01.re + sbi * q01.im);
+      m00.im = cb * q00.im - (sbr * q01.im - sbi * q01.re);
+      m10.re = cb * q10.re - (sbr * q11.re + sbi * q11.im);
+      m10.im = cb * q10.im - (sbr * q11.im - sbi * q11.re);
+      m01.re = (sbr * q00.re - sbi * q00.im) + cb * q01.re;
+      m01.im = (sbr * q00.im + sbi * q00.re) + cb * q01.im;
+      m11.re = (sbr * q10.re - sbi * q10.im) + cb * q11.re;
+      m11.im = (sbr * q10.im + sbi * q10.re) + cb * q11.im;
+      Gn[pa][pb] = n00;
+      Gn[pa][qb] = n01;
+      Gn[qa][pb] = n10;
+      Gn[qa][qb] = n11;
+      Q[pa][pb] = m00;
+      Q[pa][qb] = m01;
+      Q[qa][pb] = m10;
+      Q[qa][qb] = m11;
       __syncthreads();
-      {
-        // thread -> 2x2 block (row pair a, column pair b); J_x = [[c, s], [-conj(s), c]]
-        const int ia = tid >> 4, ib = tid & 15;
-        const int pa = rr_player(ia, rd, 32), qa = rr_player(31 - ia, rd, 32);
-        const int pb = rr_player(ib, rd, 32), qb = rr_player(31 - ib, rd, 32);
-        const T ca = (T)rot_c[ia], cb = (T)rot_c[ib];
-        const T sar = (T)rot_s[ia].re, sai = (T)rot_s[ia].im;
-        const T sbr = (T)rot_s[ib].re, sbi = (T)rot_s[ib].im;
-        const cplx<T> b00 = G[pa][pb], b01 = G[pa][qb], b10 = G[qa][pb], b11 = G[qa][qb];
-        const cplx<T> q00 = Q[pa][pb], q01 = Q[pa][qb], q10 = Q[qa][pb], q11 = Q[qa][qb];
-        // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
-        cplx<T> x00, x01, x10, x11;
-        x00.re = cb * b00.re - (sbr * b01.re + sbi * b01.im);
-        x00.im = cb * b00.im - (sbr * b01.im - sbi * b01.re);
-        x10.re = cb * b10.re - (sbr * b11.re + sbi * b11.im);
-        x10.im = cb * b10.im - (sbr * b11.im - sbi * b11.re);
-        x01.re = (sbr * b00.re - sbi * b00.im) + cb * b01.re;
-        x01.im = (sbr * b00.im + sbi * b00.re) + cb * b01.im;
-        x11.re = (sbr * b10.re - sbi * b10.im) + cb * b11.re;
-        x11.im = (sbr * b10.im + sbi * b10.re) + cb * b11.im;
-        // B' = J_a^H X: row0 = c_a X[0,:] - s_a X[1,:];  row1 = conj(s_a) X[0,:] + c_a X[1,:]
-        cplx<T> n00, n01, n10, n11;
-        n00.re = ca * x00.re - (sar * x10.re - sai * x10.im);
-        n00.im = ca * x00.im - (sar * x10.im + sai * x10.re);
-        n01.re = ca * x01.re - (sar * x11.re - sai * x11.im);
-        n01.im = ca * x01.im - (sar * x11.im + sai * x11.re);
-        n10.re = (sar * x00.re + sai * x00.im) + ca * x10.re;
-        n10.im = (sar * x00.im - sai * x00.re) + ca * x10.im;
-        n11.re = (sar * x01.re + sai * x01.im) + ca * x11.re;
-        n11.im = (sar * x01.im - sai * x01.re) + ca * x11.im;
-        // Q' = Q J_b on rows pa, qa
-        cplx<T> m00, m01, m10, m11;
-        m00.re = cb * q00.re - (sbr * q01.re + sbi * q01.im);
-        m00.im = cb * q00.im - (sbr * q01.im - sbi * q01.re);
-        m10.re = cb * q10.re - (sbr * q11.re + sbi * q11.im);
-        m10.im = cb * q10.im - (sbr * q11.im - sbi * q11.re);
-        m01.re = (sbr * q00.re - sbi * q00.im) + cb * q01.re;
-        m01.im = (sbr * q00.im + sbi * q00.re) + cb * q01.im;
-        m11.re = (sbr * q10.re - sbi * q10.im) + cb * q11.re;
-        m11.im = (sbr * q10.im + sbi * q10.re) + cb * q11.im;
-        __syncthreads();  // every block read before any write
-        G[pa][pb] = n00;
-        G[pa][qb] = n01;
-        G[qa][pb] = n10;
-        G[qa][qb] = n11;
-        Q[pa][pb] = m00;
-        Q[pa][qb] = m01;
-        Q[qa][pb] = m10;
-        Q[qa][qb] = m11;
-      }
-      __syncthreads();
+      cplx<T>(*tmp)[33] = Gc;
+      Gc = Gn;
+      Gn = tmp;
     }
     __syncthreads();
     const int f = flag;
@@ -484,10 +521,10 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   if (tid < 32) {
     int p = tid;
     if (sort_pairs && nI == 16 && nJ == 16) {
-      const T dj = G[tid][tid].re;
+      const T dj = Gc[tid][tid].re;
       int rank = 0;
       for (int i = 0; i < 32; ++i) {
-        const T di = G[i][i].re;
+        const T di = Gc[i][i].re;
         rank += (di > dj || (di == dj && i < tid)) ? 1 : 0;
       }
       p = (I < J) ? rank : (rank < 16 ? rank + 16 : rank - 16);
@@ -495,10 +532,11 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     pos[tid] = p;
   }
   __syncthreads();
-  // column-permuted copy of Q, kept in G's storage (G is no longer needed)
+  // column-permuted copy of Q in the free G buffer
+  cplx<T>(*Qp)[33] = Gn;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
-    G[i][pos[j]] = Q[i][j];
+    Qp[i][pos[j]] = Q[i][j];
   }
   __syncthreads();
 
@@ -528,8 +566,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
           for (int v = 0; v < 4; ++v) o[i][j][v] = T(0);
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
-        const cplx<T> b0 = G[ks * 4 + grp][col];
-        const cplx<T> b1 = G[ks * 4 + grp][16 + col];
+        const cplx<T> b0 = Qp[ks * 4 + grp][col];
+        const cplx<T> b1 = Qp[ks * 4 + grp][16 + col];
         cmfma<T>(o[0], av[ks], b0);
         cmfma<T>(o[1], av[ks], b1);
       }
