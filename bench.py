@@ -55,6 +55,9 @@ def parse_args(argv=None):
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU seconds for the oracle sample")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="first run a plain device copy of MIB MiB three times (a kernel of "
+                        "known traffic for scaling hardware byte counters)")
     return p.parse_args(argv)
 
 
@@ -167,6 +170,15 @@ def main(argv=None):
 
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
+    if args.copy_calibration > 0:
+        n_el = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB read + write")
+        del src, dst
     chi, n = args.chi, args.n_sites
     n_setup = setup_layers(chi)
     depth = n_setup + args.warmup + args.steps

@@ -61,6 +61,27 @@ __device__ inline cplx<T> czero() {
   return z;
 }
 
+// Four consecutive complex entries from 16-byte aligned memory (zeros when !ok).
+template <class T>
+__device__ inline void load4(bool ok, const cplx<T>* __restrict__ p, cplx<T> (&o)[4]) {
+  if (!ok) {
+    for (int t = 0; t < 4; ++t) o[t] = czero<T>();
+    return;
+  }
+  if constexpr (sizeof(T) == 4) {
+    const float4 u = *reinterpret_cast<const float4*>(p);
+    const float4 w = *reinterpret_cast<const float4*>(p + 2);
+    o[0].re = u.x; o[0].im = u.y; o[1].re = u.z; o[1].im = u.w;
+    o[2].re = w.x; o[2].im = w.y; o[3].re = w.z; o[3].im = w.w;
+  } else {
+    for (int t = 0; t < 4; ++t) {
+      const double2 u = *reinterpret_cast<const double2*>(p + t);
+      o[t].re = u.x;
+      o[t].im = u.y;
+    }
+  }
+}
+
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
   return v;
@@ -311,6 +332,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   __shared__ cplx<T> G[32][33];
   __shared__ cplx<T> G2[32][33];
   __shared__ cplx<T> Q[32][33];
+  __shared__ cplx<T> Q2[32][33];
   __shared__ double red[4];
   __shared__ int flag;
   __shared__ int pos[32];
@@ -332,12 +354,19 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   const cplx<T>* __restrict__ wJ = W + (size_t)(cJ + (okJ ? col : 0)) * R;
   cplx<T> xi[4], xj[4], ni[4], nj[4];
   auto load_chunk = [&](int r0, cplx<T>(&a)[4], cplx<T>(&b)[4]) {
+    const int rbase = r0 + grp * 4;
+    if (rbase + 3 < R) {
+      // 4 consecutive complex entries; 16-byte aligned (R is even, rbase a multiple of 4)
+      load4<T>(okI, wI + rbase, a);
+      load4<T>(okJ, wJ + rbase, b);
+    } else {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int r = r0 + grp * 4 + t;
-      const bool ok = r < R;
-      a[t] = (okI && ok) ? wI[r] : czero<T>();
-      b[t] = (okJ && ok) ? wJ[r] : czero<T>();
+      for (int t = 0; t < 4; ++t) {
+        const int r = rbase + t;
+        const bool ok = r < R;
+        a[t] = (okI && ok) ? wI[r] : czero<T>();
+        b[t] = (okJ && ok) ? wJ[r] : czero<T>();
+      }
     }
   };
   int r0 = wave * 16;
@@ -440,14 +469,23 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     z.im = T(0);
     Q[i][j] = z;
   }
-  // Each round pairs the 32 indices by the round-robin tournament; every thread owns one
-  // 2x2 block (row pair ia, column pair ib) of G and of Q.  Every wave computes the 16
-  // rotations of the round itself (lanes 0..15, FP64) and hands them to its lanes by
-  // shuffles, so a round needs a single barrier: G is double-buffered, and each Q block is
-  // read and written only by its owner.
+  // G and Q are stored in tournament-slot order: in every round slot k is paired with slot
+  // 31 - k, and thread (ia, ib) owns rows (ia, 31 - ia) and columns (ib, 31 - ib).  The
+  // circle method moves every player except player 0 down one slot per round, so each
+  // thread writes its rotated 2x2 block straight to the next round's slots (double
+  // buffers); 16 consecutive lanes then always touch 16 consecutive complex entries, which
+  // keeps the interleaved LDS accesses free of bank conflicts.  After the 31 rounds of a
+  // sweep the slots are back in natural order.  Every wave computes the 16 rotations of the
+  // round itself (lanes 0..15, FP64) and hands them to its lanes by shuffles, so a round
+  // needs a single barrier.
   cplx<T>(*Gc)[33] = G;
   cplx<T>(*Gn)[33] = G2;
+  cplx<T>(*Qc)[33] = Q;
+  cplx<T>(*Qn)[33] = Q2;
   const int ia = tid >> 4, ib = tid & 15;
+  const int ra = ia, rb2 = 31 - ia, ca0 = ib, cb2 = 31 - ib;
+  auto next_slot = [](int s) { return s >= 2 ? s - 1 : (s == 1 ? 31 : 0); };
+  const int nra = next_slot(ra), nrb = next_slot(rb2), nca = next_slot(ca0), ncb = next_slot(cb2);
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     __syncthreads();
     if (tid == 0) flag = 0;
@@ -455,7 +493,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     for (int rd = 0; rd < 31; ++rd) {
       double c = 1.0, sr = 0.0, si = 0.0;
       if (lane < 16) {
-        const int p = rr32(lane, rd), q = rr32(31 - lane, rd);
+        const int p = lane, q = 31 - lane;
         const bool did = jacobi_rotation((double)Gc[p][p].re, (double)Gc[q][q].re,
                                          (double)Gc[p][q].re, (double)Gc[p][q].im, inner_tol, c,
                                          sr, si);
@@ -463,10 +501,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
       }
       const T ca = (T)__shfl(c, ia), sar = (T)__shfl(sr, ia), sai = (T)__shfl(si, ia);
       const T cb = (T)__shfl(c, ib), sbr = (T)__shfl(sr, ib), sbi = (T)__shfl(si, ib);
-      const int pa = rr32(ia, rd), qa = rr32(31 - ia, rd);
-      const int pb = rr32(ib, rd), qb = rr32(31 - ib, rd);
-      const cplx<T> b00 = Gc[pa][pb], b01 = Gc[pa][qb], b10 = Gc[qa][pb], b11 = Gc[qa][qb];
-      const cplx<T> q00 = Q[pa][pb], q01 = Q[pa][qb], q10 = Q[qa][pb], q11 = Q[qa][qb];
+      const cplx<T> b00 = Gc[ra][ca0], b01 = Gc[ra][cb2], b10 = Gc[rb2][ca0], b11 = Gc[rb2][cb2];
+      const cplx<T> q00 = Qc[ra][ca0], q01 = Qc[ra][cb2], q10 = Qc[rb2][ca0], q11 = Qc[rb2][cb2];
       // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
       cplx<T> x00, x01, x10, x11;
       x00.re = cb * b00.re - (sbr * b01.re + sbi * b01.im);
@@ -487,7 +523,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
       n10.im = (sar * x00.im - sai * x00.re) + ca * x10.im;
       n11.re = (sar * x01.re + sai * x01.im) + ca * x11.re;
       n11.im = (sar * x01.im - sai * x01.re) + ca * x11.im;
-      // Q' = Q J_b on rows pa, qa
+      // Q' = Q J_b (rows ra, rb2 of Q are a plain partition; its columns follow the slots)
       cplx<T> m00, m01, m10, m11;
       m00.re = cb * q00.re - (sbr * q01.re + sbi * q01.im);
       m00.im = cb * q00.im - (sbr * q01.im - sbi * q01.re);
@@ -497,18 +533,21 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
       m01.im = (sbr * q00.im + sbi * q00.re) + cb * q01.im;
       m11.re = (sbr * q10.re - sbi * q10.im) + cb * q11.re;
       m11.im = (sbr * q10.im + sbi * q10.re) + cb * q11.im;
-      Gn[pa][pb] = n00;
-      Gn[pa][qb] = n01;
-      Gn[qa][pb] = n10;
-      Gn[qa][qb] = n11;
-      Q[pa][pb] = m00;
-      Q[pa][qb] = m01;
-      Q[qa][pb] = m10;
-      Q[qa][qb] = m11;
+      Gn[nra][nca] = n00;
+      Gn[nra][ncb] = n01;
+      Gn[nrb][nca] = n10;
+      Gn[nrb][ncb] = n11;
+      Qn[ra][nca] = m00;
+      Qn[ra][ncb] = m01;
+      Qn[rb2][nca] = m10;
+      Qn[rb2][ncb] = m11;
       __syncthreads();
-      cplx<T>(*tmp)[33] = Gc;
+      cplx<T>(*tg)[33] = Gc;
       Gc = Gn;
-      Gn = tmp;
+      Gn = tg;
+      cplx<T>(*tq)[33] = Qc;
+      Qc = Qn;
+      Qn = tq;
     }
     __syncthreads();
     const int f = flag;
@@ -536,7 +575,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   cplx<T>(*Qp)[33] = Gn;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
-    Qp[i][pos[j]] = Q[i][j];
+    Qp[i][pos[j]] = Qc[i][j];
   }
   __syncthreads();
 
@@ -576,13 +615,26 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
         const bool okc = jt == 0 ? jj < nI : jj - 16 < nJ;
         const int cidx = jt == 0 ? cI + jj : cJ + jj - 16;
         if (!okc) continue;
+        cplx<T>* __restrict__ dst = M + (size_t)cidx * rows;
+        if constexpr (sizeof(T) == 4) {
+          // f32 layout: this lane's four values are rows rb + 4*grp + 0..3 of one column
+          const int r4 = rb + 4 * grp;
+          if (r4 + 3 < rows) {
+            float4 u, w;
+            u.x = o[jt][0][0]; u.y = o[jt][1][0]; u.z = o[jt][0][1]; u.w = o[jt][1][1];
+            w.x = o[jt][0][2]; w.y = o[jt][1][2]; w.z = o[jt][0][3]; w.w = o[jt][1][3];
+            *reinterpret_cast<float4*>(dst + r4) = u;
+            *reinterpret_cast<float4*>(dst + r4 + 2) = w;
+            continue;
+          }
+        }
         for (int v = 0; v < 4; ++v) {
           const int rr = rb + Mfma<T>::row(lane, v);
           if (rr < rows) {
             cplx<T> z;
             z.re = o[jt][0][v];
             z.im = o[jt][1][v];
-            M[(size_t)cidx * rows + rr] = z;
+            dst[rr] = z;
           }
         }
       }
