@@ -56,8 +56,9 @@ def parse_args(argv=None):
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU seconds for the oracle sample")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                   help="first run a plain device copy of MIB MiB three times (a kernel of "
-                        "known traffic for scaling hardware byte counters)")
+                   help="first run a plain elementwise copy kernel (MIB MiB read, MIB MiB "
+                        "written) three times, a kernel of known traffic for scaling hardware "
+                        "byte counters")
     return p.parse_args(argv)
 
 
@@ -171,13 +172,15 @@ def main(argv=None):
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
     if args.copy_calibration > 0:
+        # an elementwise kernel that reads MIB MiB and writes MIB MiB (dst = 2 * src)
         n_el = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n_el, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 x {args.copy_calibration} MiB read + write")
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB read + write (torch.mul)")
         del src, dst
     chi, n = args.chi, args.n_sites
     n_setup = setup_layers(chi)
