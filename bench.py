@@ -102,6 +102,25 @@ def run_path(precision, layers, n_setup, warmup, steps, n_sites, chi, stream):
                "ms_per_step": 1e3 * elapsed / steps, "kernels": kstats, "layers": per_layer}
 
 
+def measured_traffic(kernel_name: str, precision: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, valid only while the kernel source is the one the counters were taken on."""
+    import hashlib
+    import re
+    summary = os.path.join(ROOT, "profiles", f"{kernel_name}_{precision}_N1024_chi256.md")
+    src = os.path.join(ROOT, "paper_2312_02667_amd", "csrc", "ptebd_kernels.hip")
+    try:
+        text = open(summary).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
+    m_val = re.search(r"hbm_bytes_per_launch: ([0-9.eE+-]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != digest:
+        return None
+    return float(m_val.group(1))
+
+
 def roofline(kstats, precision):
     name = max(kstats, key=lambda k: kstats[k]["total_ms"])
     ks = kstats[name]
@@ -116,7 +135,8 @@ def roofline(kstats, precision):
         achieved = ks["bytes"] / secs / 1e9
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
                "frac": achieved / HBM_GBS}
-    out.update({"traffic": None, "kernel": name, "launches": ks["launches"],
+    traffic = measured_traffic("jacobi_round", precision) if name == "jacobi" else None
+    out.update({"traffic": traffic, "kernel": name, "launches": ks["launches"],
                 "avg_launch_ms": ks["total_ms"] / launches,
                 "flops_per_launch": ks["flops"] / launches,
                 "bytes_per_launch": ks["bytes"] / launches})
