@@ -173,6 +173,11 @@ int ptebd_get_lambda(ptebd_mps_t h, int s, int bond, double* out, int cap, int* 
 int ptebd_export(ptebd_mps_t h, int s, double* gamma, size_t gamma_cap, double* lambda,
                  size_t lambda_cap);
 
+/* Export only Gamma[q] of state s (C order (a, s, m), complex128, gamma_cap doubles
+ * >= 4 chi_q chi_{q+1}); *dims_out (optional, 2 ints) receives chi_q, chi_{q+1}. */
+int ptebd_export_site(ptebd_mps_t h, int s, int q, double* gamma, size_t gamma_cap,
+                      int32_t* dims_out);
+
 /* Import state s from host data in the export format; dims = chi_0..chi_N
  * (chi_0 = chi_N = 1, every chi_i <= chi_cap).  Resets the nu / eps products to 1. */
 int ptebd_import(ptebd_mps_t h, int s, const int32_t* dims, const double* gamma,

@@ -949,6 +949,40 @@ int ptebd_export(ptebd_mps_t h, int s, double* gamma, size_t gamma_cap, double* 
   return PTEBD_OK;
 }
 
+int ptebd_export_site(ptebd_mps_t h, int s, int q, double* gamma, size_t gamma_cap,
+                      int32_t* dims_out) {
+  PT_CHECK(check_state(h, s));
+  const StateInfo& si = h->st[s];
+  if (q < 0 || q >= si.n) return fail(PTEBD_EINVAL, "site out of range");
+  const int cl = si.dims[q], cm = si.dims[q + 1];
+  const size_t cnt = 2 * (size_t)cl * cm;
+  if (!gamma || gamma_cap < 2 * cnt) return fail(PTEBD_EINVAL, "export buffer too small");
+  PT_CHECK(set_device(h));
+  PT_HIP(hipStreamSynchronize(h->stream));
+  std::vector<char> tmp(cnt * h->celem);
+  PT_HIP(hipMemcpy(tmp.data(), h->gamma_slot(s, q), cnt * h->celem, hipMemcpyDeviceToHost));
+  for (int a = 0; a < cl; ++a)
+    for (int p = 0; p < 2; ++p)
+      for (int m = 0; m < cm; ++m) {
+        const size_t src = (size_t)p * cl * cm + (size_t)m * cl + a;
+        const size_t dst = 2 * (((size_t)a * 2 + p) * cm + m);
+        if (h->precision == PTEBD_FP64) {
+          const cplx<double> z = ((const cplx<double>*)tmp.data())[src];
+          gamma[dst] = z.re;
+          gamma[dst + 1] = z.im;
+        } else {
+          const cplx<float> z = ((const cplx<float>*)tmp.data())[src];
+          gamma[dst] = z.re;
+          gamma[dst + 1] = z.im;
+        }
+      }
+  if (dims_out) {
+    dims_out[0] = cl;
+    dims_out[1] = cm;
+  }
+  return PTEBD_OK;
+}
+
 int ptebd_import(ptebd_mps_t h, int s, const int32_t* dims, const double* gamma,
                  const double* lambda) {
   PT_CHECK(check_state(h, s));

@@ -86,6 +86,8 @@ _SIGS = {
     "ptebd_export": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, ctypes.c_size_t, _dp,
                                      ctypes.c_size_t]),
     "ptebd_import": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _dp, _dp]),
+    "ptebd_export_site": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp,
+                                          ctypes.c_size_t, _i32p]),
     "ptebd_debug_theta": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp, _dp]),
     "ptebd_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "ptebd_get_kernel_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
@@ -281,6 +283,16 @@ class MPS:
             lambdas.append(lam[off:off + dims[i]].copy())
             off += dims[i]
         return gammas, lambdas
+
+    def export_site(self, q: int, s: int = 0) -> np.ndarray:
+        """Gamma[q] of state s as a complex128 (chi_q, 2, chi_{q+1}) array."""
+        dims = self.bond_dims(s)
+        n = 4 * dims[q] * dims[q + 1]
+        g = np.zeros(n, np.float64)
+        d = np.zeros(2, np.int32)
+        _check(lib().ptebd_export_site(self._h, s, int(q), _ptr(g, ctypes.c_double), n,
+                                       _ptr(d, ctypes.c_int32)))
+        return g.view(np.complex128).reshape(int(d[0]), 2, int(d[1])).copy()
 
     def import_state(self, gammas, lambdas, s: int = 0):
         dims = np.array([len(x) for x in lambdas], np.int32)
