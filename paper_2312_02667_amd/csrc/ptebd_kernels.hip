@@ -333,6 +333,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   __shared__ cplx<T> G2[32][33];
   __shared__ cplx<T> Q[32][33];
   __shared__ cplx<T> Q2[32][33];
+  __shared__ T P[16][4];  // one round's rotations: c, Re s, Im s
   __shared__ double red[4];
   __shared__ int flag;
   __shared__ int pos[32];
@@ -476,8 +477,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   // buffers); 16 consecutive lanes then always touch 16 consecutive complex entries, which
   // keeps the interleaved LDS accesses free of bank conflicts.  After the 31 rounds of a
   // sweep the slots are back in natural order.  Every wave computes the 16 rotations of the
-  // round itself (lanes 0..15, FP64) and hands them to its lanes by shuffles, so a round
-  // needs a single barrier.
+  // round's 16 rotations are computed once, by lanes 0..15 of wave 0 in FP64, and handed to
+  // every thread through LDS.
   cplx<T>(*Gc)[33] = G;
   cplx<T>(*Gn)[33] = G2;
   cplx<T>(*Qc)[33] = Q;
@@ -491,16 +492,20 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     if (tid == 0) flag = 0;
     __syncthreads();
     for (int rd = 0; rd < 31; ++rd) {
-      double c = 1.0, sr = 0.0, si = 0.0;
-      if (lane < 16) {
-        const int p = lane, q = 31 - lane;
+      if (tid < 16) {
+        const int p = tid, q = 31 - tid;
+        double c, sr, si;
         const bool did = jacobi_rotation((double)Gc[p][p].re, (double)Gc[q][q].re,
                                          (double)Gc[p][q].re, (double)Gc[p][q].im, inner_tol, c,
                                          sr, si);
-        if (did && wave == 0) flag = 1;
+        if (did) flag = 1;
+        P[tid][0] = (T)c;
+        P[tid][1] = (T)sr;
+        P[tid][2] = (T)si;
       }
-      const T ca = (T)__shfl(c, ia), sar = (T)__shfl(sr, ia), sai = (T)__shfl(si, ia);
-      const T cb = (T)__shfl(c, ib), sbr = (T)__shfl(sr, ib), sbi = (T)__shfl(si, ib);
+      __syncthreads();
+      const T ca = P[ia][0], sar = P[ia][1], sai = P[ia][2];
+      const T cb = P[ib][0], sbr = P[ib][1], sbi = P[ib][2];
       const cplx<T> b00 = Gc[ra][ca0], b01 = Gc[ra][cb2], b10 = Gc[rb2][ca0], b11 = Gc[rb2][cb2];
       const cplx<T> q00 = Qc[ra][ca0], q01 = Qc[ra][cb2], q10 = Qc[rb2][ca0], q11 = Qc[rb2][cb2];
       // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
