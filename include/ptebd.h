@@ -58,10 +58,23 @@ extern "C" {
                          Jacobi rotation angles, singular values, eps, nu, Lambda and
                          the Lambda^{-1} divisions in FP64 */
 
+/* On the FP32 path every truncation (gates and tSU) drops the singular values
+ * sigma <= max(cutoff, PTEBD_FP32_CUTOFF_FLOOR) sigma_1.  Rounding in FP32 theta turns the
+ * exact zeros of a rank-deficient theta (CZ, SWAP, product gates) into singular values of up
+ * to a few 1e-9 sigma_1, and keeping them would put noise directions, divided by Lambda,
+ * into Gamma.  The weight so dropped is below 1.5e-14 sigma_1^2 per value.  Equal to 2^-23. */
+#define PTEBD_FP32_CUTOFF_FLOOR 1.1920928955078125e-07
+
 /* ------------------------------------------------------------------ layer flags */
 #define PTEBD_FLAG_NO_STABILIZE 1  /* nu_i = 1 (norm-stabilization ablation, Sec. III.C.1) */
 #define PTEBD_FLAG_RELATIVE_EPS 2  /* eps_i = discarded sigma^2 / sum sigma^2 (keeps each bond's
                                       local norm); default: the literal discarded sigma^2 */
+#define PTEBD_FLAG_COMPLEMENT_EPS 4 /* eps_i = 1 - kept sigma^2, so that nu_i rescales the kept
+                                      values to unit norm.  All three readings of Theorem 1's
+                                      local error agree on a normalized canonical input; this
+                                      one keeps the stabilized norm near 1 over long circuits
+                                      (Sec. V.B), the literal one lets it grow under heavy
+                                      truncation.  Not combinable with RELATIVE_EPS. */
 
 typedef struct ptebd_mps* ptebd_mps_t;
 
@@ -121,9 +134,11 @@ int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int i
  *   gates        [n_gates * 32] doubles: 16 complex128 per gate (see conventions);
  *   chi_max      >= 1 and <= the state's chi_cap: bond-dimension bound chi;
  *   cutoff       >= 0: singular values sigma <= cutoff * sigma_1 are always dropped
- *                (their weight counts in eps_i);
+ *                (their weight counts in eps_i); on the FP32 path the cutoff is at least
+ *                PTEBD_FP32_CUTOFF_FLOOR;
  *   ptsu_steps   g >= 0 PtSU steps run when some gate of the layer had r > chi_max;
- *   flags        0 or an OR of PTEBD_FLAG_NO_STABILIZE, PTEBD_FLAG_RELATIVE_EPS;
+ *   flags        0 or an OR of PTEBD_FLAG_NO_STABILIZE and one of PTEBD_FLAG_RELATIVE_EPS,
+ *                PTEBD_FLAG_COMPLEMENT_EPS (both eps flags: EINVAL);
  *   stats        optional per-layer statistics (see ptebd_layer_stats).
  * The gates of one state must act on disjoint sites (else EOVERLAP).  The call enqueues
  * the layer on the handle's stream and returns after it has completed (the new bond

@@ -97,17 +97,23 @@ def two_site_theta(mps: VidalMPS, q: int, gate) -> np.ndarray:
     return theta.reshape(len(ll) * 2, 2 * len(lr))
 
 
+EPS_READINGS = ("literal", "relative", "complement")
+
+
 def bond_update(mps: VidalMPS, q: int, gate, chi_max: int | None, cutoff: float,
-                stabilize: bool = True, relative_eps: bool = False) -> dict:
+                stabilize: bool = True, eps_reading: str = "literal") -> dict:
     """One TEBD procedure at bond q+1 with truncation and norm stabilization.
 
     Steps (Sec. II.C; Sec. III.B; Theorem 1; Eq. (lren)):
       1. theta = gate . (Lambda[q] Gamma[q] Lambda[q+1] Gamma[q+1] Lambda[q+2]);
       2. SVD theta = X S Y^dagger;
       3. r = #{sigma > cutoff * sigma_1}; k = min(chi_max, r) (k = r when chi_max is None);
-         eps = sum of the discarded sigma^2 (Theorem 1's local error, taken literally on the
-         Schmidt values of theta); with ``relative_eps`` it is divided by sum sigma^2, which
-         equals the literal value on a normalized canonical input;
+         eps is Theorem 1's local error, which on a normalized canonical input is the
+         discarded weight, sum_{a >= k} sigma_a^2 = 1 - sum_{a < k} sigma_a^2 (there the
+         Schmidt values have unit norm).  Away from that input the two forms differ, and
+         ``eps_reading`` picks one: "literal" the discarded sigma^2; "relative" the discarded
+         sigma^2 divided by sum sigma^2; "complement" 1 - sum of the kept sigma^2, which
+         makes nu rescale the kept values to unit norm;
       4. nu = (1 - eps)^(-1/2) when stabilizing, else 1;  Lambda[q+1] = nu * S[:k];
       5. Gamma[q] = X[:, :k] / Lambda[q],  Gamma[q+1] = Y^dagger[:k] / Lambda[q+2].
     """
@@ -118,9 +124,14 @@ def bond_update(mps: VidalMPS, q: int, gate, chi_max: int | None, cutoff: float,
         raise AnnihilatedError(f"two-site wavefunction at q={q} vanished")
     r = int(np.count_nonzero(s > cutoff * s[0]))
     k = r if chi_max is None else min(int(chi_max), r)
-    eps = float(np.sum(s[k:] ** 2))
-    if relative_eps:
-        eps = eps / float(np.sum(s ** 2))
+    if eps_reading == "literal":
+        eps = float(np.sum(s[k:] ** 2))
+    elif eps_reading == "relative":
+        eps = float(np.sum(s[k:] ** 2)) / float(np.sum(s ** 2))
+    elif eps_reading == "complement":
+        eps = 1.0 - float(np.sum(s[:k] ** 2))
+    else:
+        raise ValueError(f"eps_reading must be one of {EPS_READINGS}")
     if stabilize:
         if eps >= 1.0:
             raise AnnihilatedError(f"discarded weight {eps} >= 1 at q={q}")
@@ -160,7 +171,7 @@ def ptsu_step(mps: VidalMPS, cutoff: float) -> None:
 
 
 def apply_layer(mps: VidalMPS, bonds, gates, chi_max: int, cutoff: float = 1e-12,
-                ptsu_steps: int = 0, stabilize: bool = True, relative_eps: bool = False):
+                ptsu_steps: int = 0, stabilize: bool = True, eps_reading: str = "literal"):
     """One pTEBD step (Algorithm 1): parallel TEBD on every gate of the layer with the
     per-bond truncation to chi_max and norm stabilization; if any gate's rank exceeded
     chi_max the layer was compressed and ``ptsu_steps`` PtSU steps follow (IPMC, Sec. III.E).
@@ -174,7 +185,7 @@ def apply_layer(mps: VidalMPS, bonds, gates, chi_max: int, cutoff: float = 1e-12
     order = np.argsort(bonds, kind="stable")
     stats = [None] * len(bonds)
     for idx in order:
-        st = bond_update(mps, bonds[idx], gates[idx], chi_max, cutoff, stabilize, relative_eps)
+        st = bond_update(mps, bonds[idx], gates[idx], chi_max, cutoff, stabilize, eps_reading)
         mps.prod_nu *= st["nu"]
         mps.prod_one_minus_eps *= (1.0 - st["eps"])
         stats[idx] = st

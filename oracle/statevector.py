@@ -52,3 +52,18 @@ def schmidt_values(psi: np.ndarray, n_sites: int, bond: int) -> np.ndarray:
     """Singular values of Psi reshaped with sites [0, bond) as rows (Sec. II.B)."""
     m = psi.reshape(2 ** bond, 2 ** (n_sites - bond))
     return np.linalg.svd(m, compute_uv=False)
+
+
+def apply_one(psi: np.ndarray, n_sites: int, q: int, u: np.ndarray) -> np.ndarray:
+    """A single-qubit gate u[s', s] on qubit q."""
+    v = psi.reshape(2 ** q, 2, 2 ** (n_sites - q - 1))
+    return np.einsum("ij,ajb->aib", np.asarray(u, np.complex128), v).reshape(-1)
+
+
+def apply_pair(psi: np.ndarray, n_sites: int, qa: int, qb: int, gate: np.ndarray) -> np.ndarray:
+    """A two-qubit gate U[(s'_a s'_b), (s_a s_b)] on any two distinct qubits (qa the high bit),
+    applied by moving the two qubit axes of the amplitude tensor to the front."""
+    t = psi.reshape((2,) * n_sites)
+    t = np.moveaxis(t, (qa, qb), (0, 1)).reshape(4, -1)
+    t = (np.asarray(gate, np.complex128) @ t).reshape((2, 2) + (2,) * (n_sites - 2))
+    return np.moveaxis(t, (0, 1), (qa, qb)).reshape(-1)

@@ -286,7 +286,7 @@ int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, con
 // One batch of independent bond updates (all gates of a layer, or one PtSU half-step).
 template <class T>
 int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, double cutoff,
-                int stabilize, int relative_eps, UpdateResult* res) {
+                int stabilize, int eps_mode, UpdateResult* res) {
   const int n = (int)items.size();
   res->k.assign(n, 0);
   res->r.assign(n, 0);
@@ -319,7 +319,7 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
     // bounded by it; singular values beyond it are rounding noise of the precision.
     d.chi_max = chi_max > 0 ? chi_max : d.cm;
     d.stabilize = stabilize;
-    d.relative_eps = relative_eps;
+    d.eps_mode = eps_mode;
     woff[i] = total;
     total += (size_t)d.R * d.C;
     voff[i] = total;
@@ -418,10 +418,13 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
 }
 
 int run_updates_dispatch(ptebd_mps* h, const std::vector<Item>& items, int chi_max,
-                         double cutoff, int stabilize, int relative_eps, UpdateResult* res) {
+                         double cutoff, int stabilize, int eps_mode, UpdateResult* res) {
   if (h->precision == PTEBD_FP64)
-    return run_updates<double>(h, items, chi_max, cutoff, stabilize, relative_eps, res);
-  return run_updates<float>(h, items, chi_max, cutoff, stabilize, relative_eps, res);
+    return run_updates<double>(h, items, chi_max, cutoff, stabilize, eps_mode, res);
+  // FP32 theta carries rounding noise: an exactly rank-deficient theta shows spurious
+  // singular values of up to a few 1e-9 sigma_1, which the floor keeps out of Lambda.
+  return run_updates<float>(h, items, chi_max, std::max(cutoff, PTEBD_FP32_CUTOFF_FLOOR),
+                            stabilize, eps_mode, res);
 }
 
 int check_handle(ptebd_mps* h) {
@@ -632,8 +635,10 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
     return fail(PTEBD_EINVAL, "state_idx may be NULL only for a single-state handle");
   if (!(cutoff >= 0.0) || !(cutoff < 1.0)) return fail(PTEBD_EINVAL, "cutoff must be in [0, 1)");
   if (ptsu_steps < 0) return fail(PTEBD_EINVAL, "ptsu_steps < 0");
-  if (flags & ~(PTEBD_FLAG_NO_STABILIZE | PTEBD_FLAG_RELATIVE_EPS))
+  if (flags & ~(PTEBD_FLAG_NO_STABILIZE | PTEBD_FLAG_RELATIVE_EPS | PTEBD_FLAG_COMPLEMENT_EPS))
     return fail(PTEBD_EINVAL, "unknown flags");
+  if ((flags & PTEBD_FLAG_RELATIVE_EPS) && (flags & PTEBD_FLAG_COMPLEMENT_EPS))
+    return fail(PTEBD_EINVAL, "RELATIVE_EPS and COMPLEMENT_EPS exclude each other");
   if (chi_max < 1) return fail(PTEBD_EINVAL, "chi_max must be >= 1");
   std::vector<std::vector<char>> used(h->st.size());
   std::vector<Item> items(n_gates);
@@ -657,7 +662,10 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
   UpdateResult res;
   PT_CHECK(run_updates_dispatch(h, items, chi_max, cutoff,
                                 (flags & PTEBD_FLAG_NO_STABILIZE) ? 0 : 1,
-                                (flags & PTEBD_FLAG_RELATIVE_EPS) ? 1 : 0, &res));
+                                (flags & PTEBD_FLAG_RELATIVE_EPS)     ? 1
+                                : (flags & PTEBD_FLAG_COMPLEMENT_EPS) ? 2
+                                                                      : 0,
+                                &res));
   std::vector<int> trig_states;
   std::vector<char> trig(h->st.size(), 0);
   for (int i = 0; i < n_gates; ++i)

@@ -31,7 +31,7 @@ struct GateDesc {
   int32_t has_gate;        // 0: identity gate (tSU), the gate mix is skipped
   int32_t chi_max;         // truncation bound; <= 0: keep every sigma above the cutoff
   int32_t stabilize;       // 1: nu = (1 - eps)^(-1/2); 0: nu = 1
-  int32_t relative_eps;    // 1: eps = discarded sigma^2 / sum sigma^2
+  int32_t eps_mode;        // 0: discarded sigma^2; 1: that / sum sigma^2; 2: 1 - kept sigma^2
   void* gq;                // Gamma[q] slot
   void* gq1;               // Gamma[q+1] slot
   const double* lam_l;     // Lambda[q]   (cl)

@@ -746,8 +746,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
     red_w[wave] = whole;
   }
   __syncthreads();
-  double eps = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
-  if (d->relative_eps) eps /= (red_w[0] + red_w[1]) + (red_w[2] + red_w[3]);
+  const double discarded = (red_d[0] + red_d[1]) + (red_d[2] + red_d[3]);
+  const double total = (red_w[0] + red_w[1]) + (red_w[2] + red_w[3]);
+  double eps = discarded;
+  if (d->eps_mode == 1) eps = discarded / total;
+  if (d->eps_mode == 2) eps = 1.0 - (total - discarded);
   const double nu = d->stabilize ? 1.0 / sqrt(1.0 - eps) : 1.0;
   double* lam_m = d->lam_m;
   for (int j = tid; j < C; j += 256) {

@@ -28,6 +28,9 @@ FP64 = 0
 FP32 = 1
 FLAG_NO_STABILIZE = 1
 FLAG_RELATIVE_EPS = 2
+FLAG_COMPLEMENT_EPS = 4
+FP32_CUTOFF_FLOOR = 1.1920928955078125e-07  # 2^-23, PTEBD_FP32_CUTOFF_FLOOR
+EPS_FLAGS = {"literal": 0, "relative": FLAG_RELATIVE_EPS, "complement": FLAG_COMPLEMENT_EPS}
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
@@ -177,7 +180,11 @@ class MPS:
                                           int(inner_sweeps), 1 if sort_pairs else 0))
 
     def apply_layer(self, bonds, gates, chi_max: int, cutoff: float = 1e-12, ptsu_steps: int = 0,
-                    stabilize: bool = True, state_idx=None, relative_eps: bool = False) -> dict:
+                    stabilize: bool = True, state_idx=None, eps_reading: str = "literal") -> dict:
+        """One circuit layer; ``eps_reading`` is "literal" (discarded sigma^2), "relative"
+        (that over sum sigma^2) or "complement" (1 - kept sigma^2)."""
+        if eps_reading not in EPS_FLAGS:
+            raise ValueError(f"eps_reading must be one of {tuple(EPS_FLAGS)}")
         bonds = np.ascontiguousarray(bonds, dtype=np.int32)
         g = _gates_array(gates)
         n = len(bonds)
@@ -198,7 +205,7 @@ class MPS:
             self._h, n, _ptr(sidx, ctypes.c_int32) if sidx is not None else None,
             _ptr(bonds, ctypes.c_int32), _ptr(g, ctypes.c_double), int(chi_max), float(cutoff),
             int(ptsu_steps),
-            (0 if stabilize else FLAG_NO_STABILIZE) | (FLAG_RELATIVE_EPS if relative_eps else 0),
+            (0 if stabilize else FLAG_NO_STABILIZE) | EPS_FLAGS[eps_reading],
             ctypes.byref(st)))
         return {"k": k, "rank": rank, "eps": eps, "nu": nu, "sweeps": sweeps,
                 "triggered": bool(st.triggered), "ptsu_done": st.ptsu_done,

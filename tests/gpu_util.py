@@ -7,6 +7,15 @@ import numpy as np
 from oracle import ptebd_oracle as po
 
 
+# The FP32 path drops sigma <= max(cutoff, 2^-23) sigma_1 (documented in include/ptebd.h);
+# the oracle is run with the same effective cutoff when it checks that path.
+FP32_CUTOFF_FLOOR = 2.0 ** -23
+
+
+def oracle_cutoff(cutoff: float, precision: str) -> float:
+    return max(cutoff, FP32_CUTOFF_FLOOR) if precision == "fp32" else cutoff
+
+
 def say(*args):
     print(*args, flush=True)
     sys.stdout.flush()

@@ -76,3 +76,13 @@ def test_svd_batched_rejects_bad_arguments():
     assert lib.ptebd_svd_batched(5, 1, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
     a[0] = np.nan
     assert lib.ptebd_svd_batched(0, 1, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
+
+
+def test_header_constants_match_binding():
+    """The binding's flag and precision constants are the header's."""
+    src = open(os.path.join(ROOT, "include", "ptebd.h")).read()
+    defs = dict(re.findall(r"#define (PTEBD_[A-Z0-9_]+)\s+\(?(-?[0-9.e+-]+)\)?", src))
+    assert int(defs["PTEBD_FLAG_NO_STABILIZE"]) == ptebd.FLAG_NO_STABILIZE
+    assert int(defs["PTEBD_FLAG_RELATIVE_EPS"]) == ptebd.FLAG_RELATIVE_EPS
+    assert int(defs["PTEBD_FLAG_COMPLEMENT_EPS"]) == ptebd.FLAG_COMPLEMENT_EPS
+    assert float(defs["PTEBD_FP32_CUTOFF_FLOOR"]) == ptebd.FP32_CUTOFF_FLOOR == 2.0 ** -23

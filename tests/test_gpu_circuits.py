@@ -6,7 +6,7 @@ import pytest
 
 from oracle import ptebd_oracle as po
 from paper_2312_02667_amd import inputs, ptebd
-from tests.gpu_util import say, to_oracle
+from tests.gpu_util import lambda_diff, oracle_cutoff, say, to_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -20,7 +20,7 @@ def test_mixed_path_against_oracle_at_chi_256():
     m = ptebd.MPS(n, chi, "fp32")
     for li, (bonds, gates) in enumerate(layers):
         m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12)
-        po.apply_layer(ref, bonds, gates, chi_max=chi, cutoff=1e-12)
+        po.apply_layer(ref, bonds, gates, chi_max=chi, cutoff=oracle_cutoff(1e-12, "fp32"))
         if li + 1 >= 9:
             err = po.fidelity_error(ref, to_oracle(m))
             say(f"layer {li + 1}: err_F(fp32 GPU vs FP64 oracle) = {err:.3e}")
@@ -86,3 +86,117 @@ def test_deterministic_and_checkpoint_roundtrip():
     assert all(np.array_equal(x, y) for x, y in zip(ga, gd))
     for x in (a, b, c, d):
         x.close()
+
+
+# ------------------------------------------------------------------ the paper's circuit families
+
+def _run_pair(n, layers, chi, precision, reading, stabilize=True, stop_after_trigger=False,
+              check=None):
+    """Runs the GPU path and the oracle side by side; ``check(li, m, ref, st)`` after each layer.
+    Returns (gpu handle, oracle state)."""
+    ref = po.product_state(n)
+    m = ptebd.MPS(n, chi, precision)
+    for li, (bonds, gates) in enumerate(layers):
+        st = m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12, stabilize=stabilize,
+                           eps_reading=reading)
+        _, trig = po.apply_layer(ref, bonds, gates, chi_max=chi,
+                                 cutoff=oracle_cutoff(1e-12, precision),
+                                 stabilize=stabilize, eps_reading=reading)
+        assert st["triggered"] == trig
+        if check is not None:
+            check(li, m, ref, st)
+        if stop_after_trigger and trig:
+            break
+    return m, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("family", ["rqc_1d", "rqc_2d"])
+@pytest.mark.parametrize("reading", ["literal", "complement"])
+def test_random_circuits_match_oracle(precision, family, reading):
+    """RQC-1D (N=21, D=20) and RQC-2D (4x4 lattice, D=8, routed: 27 compiled layers of CZ,
+    SWAP and folded rotations) at chi_max=8: generic spectra, so Lambda is compared element
+    by element after every layer, and the final state by its fidelity with the oracle's."""
+    from paper_2312_02667_amd import circuits
+    if family == "rqc_1d":
+        n, layers = 21, circuits.rqc_1d(21, 20, seed=3)
+    else:
+        n, layers = 16, circuits.rqc_2d(4, 4, 8, seed=3)
+    tol = 1e-10 if precision == "fp64" else 2e-5
+
+    def check(li, m, ref, st):
+        say(f"{family} {precision} {reading} layer {li + 1}/{len(layers)}")
+        assert m.bond_dims() == ref.bond_dims()
+        assert lambda_diff(to_oracle(m), ref) <= tol * max(1.0, max(float(x.max()) for x in ref.lam))
+
+    m, ref = _run_pair(n, layers, 8, precision, reading, check=check)
+    err = po.fidelity_error(ref, to_oracle(m))
+    assert err <= (1e-12 if precision == "fp64" else 1e-8)
+    assert abs(m.norm() - po.norm(ref)) <= tol * po.norm(ref)
+    m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pqc_1d_exact_regime_matches_statevector(precision):
+    """PQC-1D (singlet dimers + eSWAP, N=14, D=8) with chi_max above every rank: exact."""
+    from oracle import statevector as sv
+    from paper_2312_02667_amd import circuits
+    n = 14
+    layers = circuits.pqc_1d(n, 8, seed=3)
+    m, ref = _run_pair(n, layers, 128, precision, "literal")
+    psi = sv.run_circuit(n, layers)
+    dense = po.to_dense(to_oracle(m))
+    assert 1.0 - sv.fidelity(psi, dense) <= (1e-12 if precision == "fp64" else 1e-9)
+    assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 1e-5)
+    m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pqc_2d_truncation_values_match_oracle(precision):
+    """PQC-2D (4x4, D=8) at chi_max=8.  The spin symmetry makes Schmidt values come in exactly
+    degenerate multiplets, so once a truncation splits one the kept basis (and every later
+    state) is a free choice; the comparison therefore covers the layers up to and including
+    the first truncating one, where the kept values, k and eps are unique."""
+    from paper_2312_02667_amd import circuits
+    n, layers = 16, circuits.pqc_2d(4, 4, 8, seed=3)
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    seen = {"trig": False}
+
+    def check(li, m, ref, st):
+        say(f"pqc_2d {precision} layer {li + 1}")
+        assert m.bond_dims() == ref.bond_dims()
+        assert lambda_diff(to_oracle(m), ref) <= tol
+        seen["trig"] |= st["triggered"]
+
+    m, _ = _run_pair(n, layers, 8, precision, "complement", stop_after_trigger=True, check=check)
+    assert seen["trig"]
+    m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_norm_stabilization_ablation_on_gpu(precision):
+    """Sec. V.B: RQC-1D, N=21, chi_max=4, 160 layers.  Without nu the norm decays monotonically
+    to below 1e-5; with nu under the complement reading it stays within [0.8, 1.25].  The GPU
+    norms follow the oracle's layer by layer."""
+    from paper_2312_02667_amd import circuits
+    n, depth, chi = 21, 160, 4
+    layers = circuits.rqc_1d(n, depth, seed=8)
+    rtol = 1e-9 if precision == "fp64" else 1e-3
+    for stabilize in (False, True):
+        norms = []
+
+        def check(li, m, ref, st):
+            if li % 20 == 0:
+                say(f"ablation {precision} stabilize={stabilize} layer {li + 1}")
+            nm, nr = m.norm(), po.norm(ref)
+            assert abs(nm - nr) <= rtol * nr
+            norms.append(nm)
+
+        m, _ = _run_pair(n, layers, chi, precision, "complement", stabilize=stabilize,
+                         check=check)
+        m.close()
+        norms = np.array(norms)
+        if stabilize:
+            assert np.all((norms > 0.8) & (norms < 1.25))
+        else:
+            assert np.all(np.diff(norms) <= 1e-6 * norms[:-1]) and norms[-1] < 1e-5

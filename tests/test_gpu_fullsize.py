@@ -9,7 +9,7 @@ import pytest
 
 from oracle import ptebd_oracle as po
 from paper_2312_02667_amd import inputs, ptebd
-from tests.gpu_util import say
+from tests.gpu_util import oracle_cutoff, say
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +50,8 @@ def test_full_size_layer_sampled_bonds(saturated, precision):
     for q in SAMPLED:
         i = int(np.where(bonds == q)[0][0])
         local = po.VidalMPS([g[q], g[q + 1]], [l[q], l[q + 1], l[q + 2]])
-        ref = po.bond_update(local, 0, gates[i], CHI, 1e-12, stabilize=True)
+        ref = po.bond_update(local, 0, gates[i], CHI, oracle_cutoff(1e-12, precision),
+                             stabilize=True)
         say(f"  q={q}: theta {2 * len(l[q])}x{2 * len(l[q + 2])}, k={ref['k']}")
         assert st["k"][i] == ref["k"]
         s1 = ref["sigma"][0]

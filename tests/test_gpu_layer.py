@@ -7,7 +7,7 @@ import pytest
 from oracle import ptebd_oracle as po
 from oracle import statevector as sv
 from paper_2312_02667_amd import inputs, ptebd
-from tests.gpu_util import lambda_diff, say, to_oracle
+from tests.gpu_util import lambda_diff, oracle_cutoff, say, to_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +25,7 @@ def test_small_exact_circuit(precision, seed):
     for li, (bonds, gates) in enumerate(layers):
         say(f"small circuit {precision} seed={seed} layer {li + 1}")
         st = m.apply_layer(bonds, gates, chi_max=32, cutoff=1e-12)
-        po.apply_layer(ref, bonds, gates, chi_max=32, cutoff=1e-12)
+        po.apply_layer(ref, bonds, gates, chi_max=32, cutoff=oracle_cutoff(1e-12, precision))
         assert not st["triggered"]
         assert m.bond_dims() == ref.bond_dims()
         assert lambda_diff(to_oracle(m), ref) <= lam_tol
@@ -77,24 +77,30 @@ def test_truncated_circuit_fp64_matches_oracle():
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_ptsu_and_no_stabilize_match_oracle(precision):
-    """chi_max=6 with g=2 PtSU steps (IPMC), the nu ablation flag and the relative-eps
-    reading, on N=12."""
+    """chi_max=6 with g=2 PtSU steps (IPMC), the nu ablation flag and the three eps
+    readings, on N=12."""
     n, depth, chi = 12, 8, 6
     layers = inputs.brickwork_circuit(n, depth, seed=4)
-    for stabilize, rel in ((True, False), (False, False), (True, True)):
+    for stabilize, rel in ((True, "literal"), (False, "literal"), (True, "relative"),
+                           (True, "complement"), (False, "complement")):
         ref = po.product_state(n)
         m = ptebd.MPS(n, 16, precision)
         for li, (bonds, gates) in enumerate(layers):
-            say(f"ptsu {precision} stabilize={stabilize} relative_eps={rel} layer {li + 1}")
+            say(f"ptsu {precision} stabilize={stabilize} eps_reading={rel} layer {li + 1}")
             st = m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12, ptsu_steps=2,
-                               stabilize=stabilize, relative_eps=rel)
-            _, trig = po.apply_layer(ref, bonds, gates, chi_max=chi, cutoff=1e-12, ptsu_steps=2,
-                                     stabilize=stabilize, relative_eps=rel)
+                               stabilize=stabilize, eps_reading=rel)
+            _, trig = po.apply_layer(ref, bonds, gates, chi_max=chi,
+                                     cutoff=oracle_cutoff(1e-12, precision), ptsu_steps=2,
+                                     stabilize=stabilize, eps_reading=rel)
             assert st["triggered"] == trig
             assert st["ptsu_done"] == (2 if trig else 0)
             assert m.bond_dims() == ref.bond_dims()
             assert lambda_diff(to_oracle(m), ref) <= (1e-10 if precision == "fp64" else 1e-5)
-        assert abs(m.norm() - po.norm(ref)) <= (1e-10 if precision == "fp64" else 1e-5)
+        # under the complement reading nu_i rescales by the kept weight of the FP32 theta,
+        # whose squared norm carries ~u sqrt(chi) relative rounding: a few 1e-7 per update,
+        # ~1e-5 over the ~90 updates (gates and tSU) of this circuit
+        norm_tol = 1e-10 if precision == "fp64" else (5e-5 if rel == "complement" else 1e-5)
+        assert abs(m.norm() - po.norm(ref)) <= norm_tol
         assert abs(m.canon_distance() - po.canon_distance(ref)) <= (1e-9 if precision == "fp64" else 1e-4)
         m.close()
 

@@ -325,13 +325,75 @@ def test_relative_eps_reading():
     u = inputs.haar_unitary(rng)
     a, b = mps.copy(), mps.copy()
     sa, _ = po.apply_layer(a, [3], [u], chi_max=3)
-    sb, _ = po.apply_layer(b, [3], [u], chi_max=3, relative_eps=True)
+    sb, _ = po.apply_layer(b, [3], [u], chi_max=3, eps_reading="relative")
     assert abs(sa[0]["eps"] - sb[0]["eps"]) < 1e-14
     # non-normalized input: scale the state by 1.3, local norm^2 of theta is 1.69
     c = mps.copy()
     po.scale_norm(c, 1.3)
     theta = po.two_site_theta(c, 3, u)
     before = np.sum(np.abs(theta) ** 2)
-    st, _ = po.apply_layer(c, [3], [u], chi_max=3, relative_eps=True)
+    st, _ = po.apply_layer(c, [3], [u], chi_max=3, eps_reading="relative")
     assert abs(np.sum(c.lam[4] ** 2) - before) < 1e-12 * before
     assert abs(st[0]["eps"] - np.sum(st[0]["sigma"][3:] ** 2) / before) < 1e-14
+
+
+@pytest.mark.parametrize("scale", [1.0, 0.8, 1.25])
+def test_eps_readings_on_a_scaled_canonical_state(scale):
+    """All three readings of Theorem 1's local error agree on a normalized canonical input.
+    On the same state scaled by c (theta's singular values scale by c, eps_c is the canonical
+    discarded weight), the updated bond's sum Lambda^2 is closed-form:
+    literal c^2 (1 - eps_c) / (1 - c^2 eps_c) (> c^2 when c > 1: norm 1 repels);
+    relative c^2 (the local norm is kept); complement 1 (nu rescales to unit norm)."""
+    n = 8
+    _, mps = _canonical_random_state(n, 22)
+    u = inputs.haar_unitary(np.random.default_rng(220))
+    base = mps.copy()
+    sc, _ = po.apply_layer(base, [3], [u], chi_max=3)
+    eps_c = sc[0]["eps"]
+    assert 1e-4 < eps_c < 0.5
+    expect = {"literal": scale ** 2 * (1 - eps_c) / (1 - scale ** 2 * eps_c),
+              "relative": scale ** 2, "complement": 1.0}
+    for reading, want in expect.items():
+        m = mps.copy()
+        m.lam[4] = scale * m.lam[4]        # the state, and theta at q = 3, scale by c
+        st, _ = po.apply_layer(m, [3], [u], chi_max=3, eps_reading=reading)
+        assert abs(np.sum(m.lam[4] ** 2) - want) < 1e-12
+        if scale == 1.0:
+            assert abs(st[0]["eps"] - eps_c) < 1e-13
+    with pytest.raises(ValueError):
+        po.apply_layer(mps.copy(), [3], [u], chi_max=3, eps_reading="other")
+
+
+def test_norm_stabilization_ablation_rqc_1d():
+    """Sec. V.B (the norm-vs-depth figure): without nu the norm of a truncated RQC-1D decays
+    monotonically and exponentially; with nu under the complement reading it stays near 1.
+    Under the literal reading the stabilized norm leaves that band within the same circuit
+    (norm 1 is a repelling fixed point, see the scaled-state pin above)."""
+    from paper_2312_02667_amd import circuits
+    n, depth, chi = 21, 160, 4
+    layers = circuits.rqc_1d(n, depth, seed=8)
+    states = {"none": po.product_state(n), "complement": po.product_state(n),
+              "literal": po.product_state(n)}
+    norms = {k: [] for k in states}
+    for bonds, gates in layers:
+        po.apply_layer(states["none"], bonds, gates, chi_max=chi, stabilize=False)
+        po.apply_layer(states["complement"], bonds, gates, chi_max=chi, eps_reading="complement")
+        if states["literal"] is not None:
+            try:
+                po.apply_layer(states["literal"], bonds, gates, chi_max=chi)
+            except po.AnnihilatedError:      # a discarded weight reached 1
+                states["literal"] = None
+        for k, m in states.items():
+            norms[k].append(np.inf if m is None else po.norm(m))
+    none = np.array(norms["none"])
+    assert np.all(np.diff(none) <= 1e-12)                  # monotone decay
+    assert none[-1] < 1e-5
+    # exponential: the decay rate of log n over the second and the last quarter agree
+    q = depth // 4
+    r2 = (np.log(none[2 * q]) - np.log(none[q])) / q
+    r4 = (np.log(none[-1]) - np.log(none[3 * q])) / (depth - 1 - 3 * q)
+    assert r2 < 0 and r4 < 0 and 0.5 < r4 / r2 < 2.0
+    comp = np.array(norms["complement"])
+    assert np.all((comp > 0.8) & (comp < 1.25))
+    lit = np.array(norms["literal"])
+    assert lit.max() > 1.5
