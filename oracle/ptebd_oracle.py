@@ -28,6 +28,8 @@ Functions and the passages they follow:
   * ``canon_distance`` -- the distance to the canonical form, Eq. (dist_to_cano).
   * ``canonicalize`` -- sequential SVD sweeps restoring the canonical form (the
     ``Canonicalize`` step of Algorithm 1), used by the canonical-form experiment of Sec. III.D.
+  * ``sample`` -- perfect sampling of bit strings from a canonical MPS (the measurement step
+    after ``Canonicalize`` in Algorithm 1; the method of Ferris and Vidal cited there).
   * ``to_dense`` -- full contraction to a 2^N state vector (site 0 = most significant bit).
 """
 
@@ -331,6 +333,37 @@ def canonicalize(mps: VidalMPS, cutoff: float = 0.0):
     rights[0] = carry
     gam = [rights[q] / lam[q + 1][None, None, :] for q in range(n)]
     return VidalMPS(gam, lam), nrm
+
+
+def sample(mps: VidalMPS, uniforms: np.ndarray) -> np.ndarray:
+    """Perfect sampling from a state in canonical form, one bit string per row of
+    ``uniforms`` (shape (S, N), values in [0, 1)); returns uint8 bits of shape (S, N).
+
+    With the right-isometric tensors B[q] = Gamma[q] Lambda[q+1] of the canonical form, the
+    probability of sigma_q given the bits already drawn is |v B[q]_sigma|^2 / |v|^2, where the
+    row vector v is the contraction of the drawn prefix (v = (1) before site 0).  Site by
+    site: w_s = v B[q]_s for s = 0, 1; p_s = |w_s|^2; sigma_q = 0 if u < p_0 / (p_0 + p_1),
+    else 1; v = w_sigma / sqrt(p_sigma).  The decision is taken in float64.
+    """
+    n = mps.n_sites
+    u = np.asarray(uniforms, np.float64)
+    if u.ndim != 2 or u.shape[1] != n:
+        raise ValueError("uniforms must have shape (n_samples, n_sites)")
+    b = [mps.gam[q] * mps.lam[q + 1][None, None, :] for q in range(n)]
+    bits = np.zeros(u.shape, np.uint8)
+    for i in range(u.shape[0]):
+        v = np.ones(1, np.complex128)
+        for q in range(n):
+            w0 = v @ b[q][:, 0, :]
+            w1 = v @ b[q][:, 1, :]
+            p0 = float(np.vdot(w0, w0).real)
+            p1 = float(np.vdot(w1, w1).real)
+            if u[i, q] < p0 / (p0 + p1):
+                v = w0 / np.sqrt(p0)
+            else:
+                bits[i, q] = 1
+                v = w1 / np.sqrt(p1)
+    return bits
 
 
 def scale_norm(mps: VidalMPS, factor: float) -> None:

@@ -476,9 +476,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   // thread writes its rotated 2x2 block straight to the next round's slots (double
   // buffers); 16 consecutive lanes then always touch 16 consecutive complex entries, which
   // keeps the interleaved LDS accesses free of bank conflicts.  After the 31 rounds of a
-  // sweep the slots are back in natural order.  Every wave computes the 16 rotations of the
-  // round's 16 rotations are computed once, by lanes 0..15 of wave 0 in FP64, and handed to
-  // every thread through LDS.
+  // sweep the slots are back in natural order.  A round's 16 rotations are computed once,
+  // by lanes 0..15 of wave 0 in FP64, and handed to every thread through LDS.
   cplx<T>(*Gc)[33] = G;
   cplx<T>(*Gn)[33] = G2;
   cplx<T>(*Qc)[33] = Q;

@@ -397,3 +397,72 @@ def test_norm_stabilization_ablation_rqc_1d():
     assert np.all((comp > 0.8) & (comp < 1.25))
     lit = np.array(norms["literal"])
     assert lit.max() > 1.5
+
+
+def _dense_conditional_sample(psi, n, u):
+    """Draws bits site by site from the exact conditional probabilities of the dense state."""
+    p = np.abs(psi) ** 2
+    bits = np.zeros(n, np.uint8)
+    block = p.reshape(1, -1)
+    for q in range(n):
+        block = block.reshape(2, -1)
+        p0, p1 = block[0].sum(), block[1].sum()
+        b = 0 if u[q] < p0 / (p0 + p1) else 1
+        bits[q] = b
+        block = block[b]
+    return bits
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sampling_matches_dense_conditional_sampling(seed):
+    """Perfect sampling on the canonicalized MPS equals inverse-CDF sampling from the exact
+    conditional probabilities of the state vector, bit for bit, for the same uniforms."""
+    n = 8
+    m = po.product_state(n)
+    for bonds, gates in inputs.brickwork_circuit(n, 6, seed):
+        po.apply_layer(m, bonds, gates, chi_max=4)      # a truncated, non-canonical state
+    psi = po.to_dense(m)
+    can, nrm = po.canonicalize(m)
+    rng = np.random.default_rng(100 + seed)
+    u = rng.random((200, n))
+    got = po.sample(can, u)
+    for i in range(len(u)):
+        assert np.array_equal(got[i], _dense_conditional_sample(psi, n, u[i]))
+    assert abs(nrm - np.linalg.norm(psi)) < 1e-12
+
+
+def test_sampling_special_cases_and_frequencies():
+    """Product and GHZ states, and empirical frequencies against |psi|^2 (N = 5)."""
+    n = 5
+    # |1 0 1 1 0>: deterministic bits
+    m = po.product_state(n)
+    x = np.array([[0, 1], [1, 0]], np.complex128)
+    for q in (0, 2, 3):
+        po.apply_layer(m, [q if q < n - 1 else q - 1],
+                       [np.kron(x, np.eye(2)) if q < n - 1 else np.kron(np.eye(2), x)], chi_max=4)
+    can, _ = po.canonicalize(m)
+    rng = np.random.default_rng(5)
+    assert np.all(po.sample(can, rng.random((50, n))) == np.array([1, 0, 1, 1, 0], np.uint8))
+    # GHZ: all bits equal, each value with probability 1/2
+    h = np.array([[1, 1], [1, -1]], np.complex128) / np.sqrt(2)
+    cnot = np.eye(4, dtype=np.complex128)[[0, 1, 3, 2]]
+    g = po.product_state(n)
+    po.apply_layer(g, [0], [cnot @ np.kron(h, np.eye(2))], chi_max=8)
+    for q in range(1, n - 1):
+        po.apply_layer(g, [q], [cnot], chi_max=8)
+    can, _ = po.canonicalize(g)
+    bits = po.sample(can, rng.random((4000, n)))
+    assert np.all(bits == bits[:, :1])
+    assert abs(bits[:, 0].mean() - 0.5) < 0.03
+    # a random 5-qubit state: outcome frequencies within 5 standard deviations of |psi|^2
+    r = po.product_state(n)
+    for bonds, gates in inputs.brickwork_circuit(n, 6, 9):
+        po.apply_layer(r, bonds, gates, chi_max=8)
+    psi = po.to_dense(r)
+    prob = np.abs(psi) ** 2 / np.sum(np.abs(psi) ** 2)
+    can, _ = po.canonicalize(r)
+    s = 20000
+    bits = po.sample(can, rng.random((s, n)))
+    idx = bits.astype(np.int64) @ (1 << np.arange(n - 1, -1, -1))
+    freq = np.bincount(idx, minlength=2 ** n) / s
+    assert np.all(np.abs(freq - prob) <= 5 * np.sqrt(prob * (1 - prob) / s) + 1e-12)
