@@ -59,11 +59,13 @@ extern "C" {
                          the Lambda^{-1} divisions in FP64 */
 
 /* On the FP32 path every truncation (gates and tSU) drops the singular values
- * sigma <= max(cutoff, PTEBD_FP32_CUTOFF_FLOOR) sigma_1.  Rounding in FP32 theta turns the
- * exact zeros of a rank-deficient theta (CZ, SWAP, product gates) into singular values of up
- * to a few 1e-9 sigma_1, and keeping them would put noise directions, divided by Lambda,
- * into Gamma.  The weight so dropped is below 1.5e-14 sigma_1^2 per value.  Equal to 2^-23. */
-#define PTEBD_FP32_CUTOFF_FLOOR 1.1920928955078125e-07
+ * sigma <= max(cutoff, PTEBD_FP32_CUTOFF_FLOOR) sigma_1.  The exact zeros of a rank-deficient
+ * theta (CZ, SWAP, product gates) come out of FP32 arithmetic as rounding residues: the SVD
+ * stops rotating a column once its norm is below 16 u (u = 2^-24) times its partner's, so a
+ * residue can keep up to 2^-20 sigma_1; keeping it would put a noise direction, divided by
+ * Lambda, into Gamma.  The floor is twice that level, 2^-19; the weight it drops is below
+ * 3.7e-12 sigma_1^2 per value. */
+#define PTEBD_FP32_CUTOFF_FLOOR 1.9073486328125e-06
 
 /* ------------------------------------------------------------------ layer flags */
 #define PTEBD_FLAG_NO_STABILIZE 1  /* nu_i = 1 (norm-stabilization ablation, Sec. III.C.1) */
@@ -148,6 +150,33 @@ int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int i
 int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
                       const int32_t* bonds, const double* gates, int chi_max, double cutoff,
                       int ptsu_steps, int flags, ptebd_layer_stats* stats);
+
+/* Restore the canonical form of state s: the Canonicalize step of Algorithm 1, done before
+ * measuring or sampling.  A left-to-right sweep of tSU steps on the pairs (0,1), (1,2), ...,
+ * (N-2,N-1), then a right-to-left sweep back (each tSU as in ptebd_ptsu: identity gate
+ * skipped, cutoff only, nu = 1), then the normalization Lambda[i] /= n on the inner bonds
+ * and Gamma[q] *= n on the inner sites, n the norm (n^2 = sum Lambda[1]^2 once canonical).
+ * Afterwards the state has unit norm and satisfies the canonical conditions of Eq.
+ * (l_r_cano); bond dimensions can only shrink (values <= cutoff * sigma_1 are dropped; the
+ * FP32 floor applies).  norm_out (may be NULL) receives n.  The 2(N-1) bond updates run one
+ * after another: the cost is sequential in N, unlike a layer.  The norm and fidelity
+ * estimates are left unchanged.
+ * Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV. */
+int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out);
+
+/* Perfect sampling of n_samples bit strings from state s, which must be in canonical form
+ * (call ptebd_canonicalize first; on any other state the draws do not follow |Psi|^2).
+ * Site by site, for every sample at once: with the prefix vector v (v = (1) at site 0) and
+ * the right-isometric B[q] = Gamma[q] Lambda[q+1], w_p = v B[q]_p (p = 0, 1),
+ * p_p = |w_p|^2, bit q = (u < p_0 / (p_0 + p_1)) ? 0 : 1, v = w_bit / sqrt(p_bit) (the method
+ * of Ferris and Vidal that Algorithm 1 cites for sampling).  The products run on MFMA in the
+ * handle's precision; p_0, p_1 and the decision are FP64.
+ *   uniforms  [n_samples * N] caller-owned doubles in [0, 1): uniforms[i * N + q] decides bit
+ *             q of sample i (the random numbers are an input, so runs are reproducible);
+ *   bits      [n_samples * N] caller-owned output, 0 or 1, same layout.
+ * Errors: EINVAL (n_samples < 0, NULL buffers, a uniform outside [0, 1)), ENOMEM, EDEVICE,
+ * ENONFINITE (a conditional probability vanished: the state was not canonical). */
+int ptebd_sample(ptebd_mps_t h, int s, int n_samples, const double* uniforms, uint8_t* bits);
 
 /* Run g PtSU steps on state s (tSU on all pairs (0,1),(2,3),..., then (1,2),(3,4),...;
  * each tSU is the TEBD procedure with the identity gate skipped, cutoff only, nu = 1). */
@@ -238,7 +267,8 @@ int ptebd_svd_batched(int precision, int batch, int m, int n, const double* a, d
 #define PTEBD_KERNEL_JACOBI 1
 #define PTEBD_KERNEL_FINALIZE 2
 #define PTEBD_KERNEL_WRITEBACK 3
-#define PTEBD_KERNEL_COUNT 4
+#define PTEBD_KERNEL_SAMPLE 4   /* ptebd_sample: one launch per site */
+#define PTEBD_KERNEL_COUNT 5
 
 typedef struct {
   double total_ms;   /* summed event-measured duration of the launches */

@@ -335,9 +335,11 @@ def canonicalize(mps: VidalMPS, cutoff: float = 0.0):
     return VidalMPS(gam, lam), nrm
 
 
-def sample(mps: VidalMPS, uniforms: np.ndarray) -> np.ndarray:
+def sample(mps: VidalMPS, uniforms: np.ndarray, return_margins: bool = False):
     """Perfect sampling from a state in canonical form, one bit string per row of
-    ``uniforms`` (shape (S, N), values in [0, 1)); returns uint8 bits of shape (S, N).
+    ``uniforms`` (shape (S, N), values in [0, 1)); returns uint8 bits of shape (S, N), and
+    with ``return_margins`` also each sample's smallest |u - p_0 / (p_0 + p_1)| along its
+    path (how close a decision came to flipping).
 
     With the right-isometric tensors B[q] = Gamma[q] Lambda[q+1] of the canonical form, the
     probability of sigma_q given the bits already drawn is |v B[q]_sigma|^2 / |v|^2, where the
@@ -351,6 +353,7 @@ def sample(mps: VidalMPS, uniforms: np.ndarray) -> np.ndarray:
         raise ValueError("uniforms must have shape (n_samples, n_sites)")
     b = [mps.gam[q] * mps.lam[q + 1][None, None, :] for q in range(n)]
     bits = np.zeros(u.shape, np.uint8)
+    margins = np.full(u.shape[0], np.inf)
     for i in range(u.shape[0]):
         v = np.ones(1, np.complex128)
         for q in range(n):
@@ -358,12 +361,13 @@ def sample(mps: VidalMPS, uniforms: np.ndarray) -> np.ndarray:
             w1 = v @ b[q][:, 1, :]
             p0 = float(np.vdot(w0, w0).real)
             p1 = float(np.vdot(w1, w1).real)
+            margins[i] = min(margins[i], abs(u[i, q] - p0 / (p0 + p1)))
             if u[i, q] < p0 / (p0 + p1):
                 v = w0 / np.sqrt(p0)
             else:
                 bits[i, q] = 1
                 v = w1 / np.sqrt(p1)
-    return bits
+    return (bits, margins) if return_margins else bits
 
 
 def scale_norm(mps: VidalMPS, factor: float) -> None:

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libptebd.so")
-SOURCES = ["ptebd_api.hip", "ptebd_kernels.hip", "ptebd_queries.hip"]
+SOURCES = ["ptebd_api.hip", "ptebd_kernels.hip", "ptebd_queries.hip", "ptebd_sample.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [
@@ -37,7 +37,7 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every source and link ``libptebd.so``; returns the library path."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs = []

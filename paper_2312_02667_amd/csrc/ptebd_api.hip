@@ -186,7 +186,7 @@ struct ptebd_mps {
   size_t celem = 16;  // bytes per complex element
   std::vector<StateInfo> st;
   DevBuf gamma, lam;
-  DevBuf work, desc, gates, outbuf, qscratch, renv, qout;
+  DevBuf work, desc, gates, outbuf, qscratch, renv, qout, aux, samp;
   HostBuf h_desc, h_gates, h_out, h_small;
   Prof prof;
   int max_sweeps = 30;
@@ -421,8 +421,8 @@ int run_updates_dispatch(ptebd_mps* h, const std::vector<Item>& items, int chi_m
                          double cutoff, int stabilize, int eps_mode, UpdateResult* res) {
   if (h->precision == PTEBD_FP64)
     return run_updates<double>(h, items, chi_max, cutoff, stabilize, eps_mode, res);
-  // FP32 theta carries rounding noise: an exactly rank-deficient theta shows spurious
-  // singular values of up to a few 1e-9 sigma_1, which the floor keeps out of Lambda.
+  // FP32 arithmetic leaves rounding residues of up to 2^-20 sigma_1 where an exactly
+  // rank-deficient theta has zero singular values; the floor keeps them out of Lambda.
   return run_updates<float>(h, items, chi_max, std::max(cutoff, PTEBD_FP32_CUTOFF_FLOOR),
                             stabilize, eps_mode, res);
 }
@@ -590,7 +590,7 @@ int ptebd_mps_create(int n_states, const int32_t* n_sites, const int32_t* chi_ca
 
 int ptebd_mps_destroy(ptebd_mps_t h) {
   if (!h) return PTEBD_OK;
-  if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+  (void)hipStreamSynchronize(h->stream);
   h->gamma.release();
   h->lam.release();
   h->work.release();
@@ -600,6 +600,8 @@ int ptebd_mps_destroy(ptebd_mps_t h) {
   h->qscratch.release();
   h->renv.release();
   h->qout.release();
+  h->aux.release();
+  h->samp.release();
   h->h_desc.release();
   h->h_gates.release();
   h->h_out.release();
@@ -719,6 +721,122 @@ int ptebd_get_kernel_stats(ptebd_mps_t h, int kind, ptebd_kernel_stats* out) {
   PT_HIP(hipStreamSynchronize(h->stream));
   h->prof.harvest();
   *out = h->prof.st[kind];
+  return PTEBD_OK;
+}
+
+int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out) {
+  PT_CHECK(check_state(h, s));
+  if (!(cutoff >= 0.0) || !(cutoff < 1.0)) return fail(PTEBD_EINVAL, "cutoff must be in [0, 1)");
+  PT_CHECK(set_device(h));
+  const int n = h->st[s].n;
+  int n_unconv = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int t = 0; t + 1 < n; ++t) {
+      const int q = pass == 0 ? t : n - 2 - t;
+      std::vector<Item> items{Item{s, q, nullptr}};
+      UpdateResult res;
+      PT_CHECK(run_updates_dispatch(h, items, 0, cutoff, 0, 0, &res));
+      n_unconv += res.n_unconverged;
+    }
+  const StateInfo& si = h->st[s];
+  // in canonical form every bond carries the whole norm: n^2 = sum Lambda[1]^2
+  std::vector<double> l1(si.dims[1]);
+  PT_HIP(hipStreamSynchronize(h->stream));
+  PT_HIP(hipMemcpy(l1.data(), h->lam_slot(s, 1), sizeof(double) * l1.size(),
+                   hipMemcpyDeviceToHost));
+  double n2 = 0.0;
+  for (double v : l1) n2 += v * v;
+  const double nrm = std::sqrt(n2);
+  if (!(nrm > 0.0) || !std::isfinite(nrm))
+    return fail(PTEBD_ENONFINITE, "canonicalize: the state norm is zero or not finite");
+  PT_CHECK(h->aux.ensure(sizeof(int32_t) * (si.n + 1)));
+  PT_HIP(hipMemcpyAsync(h->aux.p, si.dims.data(), sizeof(int32_t) * (si.n + 1),
+                        hipMemcpyHostToDevice, h->stream));
+  int max_elems = 1;
+  for (int q = 0; q < si.n; ++q) max_elems = std::max(max_elems, 2 * si.dims[q] * si.dims[q + 1]);
+  const size_t slot = 2 * (size_t)si.cap * si.cap;
+  if (h->precision == PTEBD_FP64)
+    ptebd::launch_scale_state<double>(h->gamma_slot(s, 0), slot, h->lam_slot(s, 0), si.cap,
+                                      (const int32_t*)h->aux.p, si.n, max_elems, nrm, h->stream);
+  else
+    ptebd::launch_scale_state<float>(h->gamma_slot(s, 0), slot, h->lam_slot(s, 0), si.cap,
+                                     (const int32_t*)h->aux.p, si.n, max_elems, nrm, h->stream);
+  PT_HIP(hipGetLastError());
+  PT_HIP(hipStreamSynchronize(h->stream));
+  if (norm_out) *norm_out = nrm;
+  if (n_unconv > 0) return fail(PTEBD_WNOCONV, "some SVDs reached the sweep cap");
+  return PTEBD_OK;
+}
+
+int ptebd_sample(ptebd_mps_t h, int s, int n_samples, const double* uniforms, uint8_t* bits) {
+  PT_CHECK(check_state(h, s));
+  if (n_samples < 0) return fail(PTEBD_EINVAL, "n_samples < 0");
+  if (n_samples == 0) return PTEBD_OK;
+  if (!uniforms || !bits) return fail(PTEBD_EINVAL, "uniforms / bits are NULL");
+  const StateInfo& si = h->st[s];
+  const int n = si.n;
+  const size_t cnt = (size_t)n_samples * n;
+  for (size_t e = 0; e < cnt; ++e)
+    if (!(uniforms[e] >= 0.0 && uniforms[e] < 1.0))
+      return fail(PTEBD_EINVAL, "uniforms must lie in [0, 1)");
+  PT_CHECK(set_device(h));
+  // device layout: uniforms | bits | W ping-pong | sel ping-pong | scale ping-pong | err
+  const int ldw = 2 * si.cap;
+  const size_t wbytes = h->celem * (size_t)n_samples * ldw;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_u = 0, o_b = al(o_u + sizeof(double) * cnt), o_w0 = al(o_b + cnt),
+               o_w1 = al(o_w0 + wbytes), o_s0 = al(o_w1 + wbytes),
+               o_s1 = al(o_s0 + sizeof(int32_t) * n_samples),
+               o_c0 = al(o_s1 + sizeof(int32_t) * n_samples),
+               o_c1 = al(o_c0 + sizeof(double) * n_samples),
+               o_e = al(o_c1 + sizeof(double) * n_samples), total = o_e + 256;
+  PT_CHECK(h->samp.ensure(total));
+  char* base = (char*)h->samp.p;
+  PT_HIP(hipMemcpyAsync(base + o_u, uniforms, sizeof(double) * cnt, hipMemcpyHostToDevice,
+                        h->stream));
+  PT_HIP(hipMemsetAsync(base + o_e, 0, sizeof(int32_t), h->stream));
+  Prof* pf = &h->prof;
+  for (int q = 0; q < n; ++q) {
+    const int cur = q & 1;
+    ptebd::SampleSite a;
+    a.gamma = h->gamma_slot(s, q);
+    a.lam_r = h->lam_slot(s, q + 1);
+    a.cl = si.dims[q];
+    a.cm = si.dims[q + 1];
+    a.first = q == 0;
+    a.n_samples = n_samples;
+    a.ldw = ldw;
+    a.w_in = base + (cur ? o_w0 : o_w1);
+    a.w_out = base + (cur ? o_w1 : o_w0);
+    a.sel_in = (const int32_t*)(base + (cur ? o_s0 : o_s1));
+    a.scale_in = (const double*)(base + (cur ? o_c0 : o_c1));
+    a.sel_out = (int32_t*)(base + (cur ? o_s1 : o_s0));
+    a.scale_out = (double*)(base + (cur ? o_c1 : o_c0));
+    a.u = (const double*)(base + o_u) + q;
+    a.ustride = n;
+    a.bits = (uint8_t*)(base + o_b) + q;
+    a.bstride = n;
+    a.err = (int32_t*)(base + o_e);
+    timed(pf, PTEBD_KERNEL_SAMPLE, h->stream, [&] {
+      if (h->precision == PTEBD_FP64)
+        ptebd::launch_sample_site<double>(a, h->stream);
+      else
+        ptebd::launch_sample_site<float>(a, h->stream);
+    });
+    if (pf->on) {
+      const double ce = (double)h->celem;
+      pf->st[PTEBD_KERNEL_SAMPLE].flops += 16.0 * n_samples * (double)a.cl * a.cm;
+      pf->st[PTEBD_KERNEL_SAMPLE].bytes +=
+          ce * (2.0 * a.cl * a.cm + (double)n_samples * (a.cl + 2.0 * a.cm));
+    }
+  }
+  PT_HIP(hipGetLastError());
+  int32_t err = 0;
+  PT_HIP(hipMemcpyAsync(bits, base + o_b, cnt, hipMemcpyDeviceToHost, h->stream));
+  PT_HIP(hipMemcpyAsync(&err, base + o_e, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  PT_HIP(hipStreamSynchronize(h->stream));
+  if (pf->on) pf->harvest();
+  if (err) return fail(PTEBD_ENONFINITE, "a conditional probability vanished (state not canonical?)");
   return PTEBD_OK;
 }
 

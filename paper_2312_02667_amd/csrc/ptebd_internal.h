@@ -62,6 +62,27 @@ struct LayerOut {
   int32_t cmax;
 };
 
+// Arguments of one site of perfect sampling (ptebd_sample.hip).
+struct SampleSite {
+  const void* gamma;         // Gamma[q] slot (complex T), planes cl x cm
+  const double* lam_r;       // Lambda[q+1] (cm)
+  int32_t cl, cm;            // chi_q, chi_{q+1}
+  int32_t first;             // 1 at site 0 (prefix vector (1))
+  int32_t n_samples;
+  int32_t ldw;               // row stride of the W buffers (>= 2 * max chi)
+  const void* w_in;          // previous site's rows (complex T), n_samples x ldw
+  void* w_out;               // this site's rows
+  const int32_t* sel_in;     // previous plane per sample
+  const double* scale_in;    // previous 1 / sqrt(p_sel) per sample
+  int32_t* sel_out;
+  double* scale_out;
+  const double* u;           // uniforms of this site, sample i at u[i * ustride]
+  int32_t ustride;
+  uint8_t* bits;             // bit of this site, sample i at bits[i * bstride]
+  int32_t bstride;
+  int32_t* err;              // bit0: a vanishing conditional probability
+};
+
 // Kernel launchers (ptebd_kernels.hip).  All are asynchronous on `stream`.
 template <class T>
 void launch_theta(const GateDesc* d_desc, int n_gates, int max_tiles, hipStream_t stream);
@@ -80,6 +101,14 @@ void launch_finalize(const GateDesc* d_desc, int n_gates, double cutoff, const L
 template <class T>
 void launch_writeback(const GateDesc* d_desc, int n_gates, const LayerOut& out,
                       hipStream_t stream);
+
+// Sampling and normalization kernels (ptebd_sample.hip).
+template <class T>
+void launch_sample_site(const SampleSite& a, hipStream_t stream);
+template <class T>
+void launch_scale_state(void* gamma_base, size_t slot_elems, double* lam_base, int lam_stride,
+                        const int32_t* d_dims, int n_sites, int max_elems, double nrm,
+                        hipStream_t stream);
 
 // Query kernels (ptebd_queries.hip), all FP64.
 // Column-major complex GEMM C = alpha * op(A) * op(B) + beta * C, op: 'N', 'T' or 'C'.

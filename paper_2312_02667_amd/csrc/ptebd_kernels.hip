@@ -5,92 +5,11 @@
 //   finalize_kernel  -- singular values, sort, truncation and discarded weight (Sec. III.B,
 //                       Theorem 1), norm stabilization nu (Sec. III.C.2, Eq. (lren))
 //   writeback_kernel -- Vidal regauge with Lambda^{-1} (Sec. II.C) into the state arena
+#include "ptebd_device.h"
 #include "ptebd_internal.h"
 
 namespace ptebd {
 namespace {
-
-// ---------------------------------------------------------------- MFMA wrappers
-// 16x16x4 MFMA.  Operand lane layout (both precisions): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16].  Result: 4 values per lane in column l%16; their rows differ between the
-// f32 and f64 instructions (checked on gfx950): f32 rows 4*(l/16)+v, f64 rows l/16+4v.
-template <class T>
-struct Mfma;
-
-template <>
-struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  __device__ static inline v4 op(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
-
-template <>
-struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  __device__ static inline v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
-
-// acc += a * b (complex); acc[0] real part, acc[1] imaginary part.
-template <class T>
-__device__ inline void cmfma(typename Mfma<T>::v4 (&acc)[2], cplx<T> a, cplx<T> b) {
-  acc[0] = Mfma<T>::op(a.re, b.re, acc[0]);
-  acc[0] = Mfma<T>::op(-a.im, b.im, acc[0]);
-  acc[1] = Mfma<T>::op(a.re, b.im, acc[1]);
-  acc[1] = Mfma<T>::op(a.im, b.re, acc[1]);
-}
-
-// acc += conj(x) * y (complex), the Gram-matrix update.
-template <class T>
-__device__ inline void gram_mfma(typename Mfma<T>::v4 (&acc)[2], cplx<T> x, cplx<T> y) {
-  acc[0] = Mfma<T>::op(x.re, y.re, acc[0]);
-  acc[0] = Mfma<T>::op(x.im, y.im, acc[0]);
-  acc[1] = Mfma<T>::op(x.re, y.im, acc[1]);
-  acc[1] = Mfma<T>::op(-x.im, y.re, acc[1]);
-}
-
-template <class T>
-__device__ inline cplx<T> czero() {
-  cplx<T> z;
-  z.re = T(0);
-  z.im = T(0);
-  return z;
-}
-
-// Four consecutive complex entries from 16-byte aligned memory (zeros when !ok).
-template <class T>
-__device__ inline void load4(bool ok, const cplx<T>* __restrict__ p, cplx<T> (&o)[4]) {
-  if (!ok) {
-    for (int t = 0; t < 4; ++t) o[t] = czero<T>();
-    return;
-  }
-  if constexpr (sizeof(T) == 4) {
-    const float4 u = *reinterpret_cast<const float4*>(p);
-    const float4 w = *reinterpret_cast<const float4*>(p + 2);
-    o[0].re = u.x; o[0].im = u.y; o[1].re = u.z; o[1].im = u.w;
-    o[2].re = w.x; o[2].im = w.y; o[3].re = w.z; o[3].im = w.w;
-  } else {
-    for (int t = 0; t < 4; ++t) {
-      const double2 u = *reinterpret_cast<const double2*>(p + t);
-      o[t].re = u.x;
-      o[t].im = u.y;
-    }
-  }
-}
-
-__device__ inline double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
 // Round-robin (circle method) tournament: player in `slot` during `round`, for an even
 // number of players; slot 0 is fixed, the others rotate.  Pairs are (p, nplayers-1-p).
@@ -125,7 +44,9 @@ __device__ inline double rcp_f64(double x) {
 // Schur step with the phase of g factored out): J = [[c, s], [-conj(s), c]] with
 // zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
 // s = t c g/|g|; J^H [[a, g], [conj g, b]] J is diagonal.  Identity when
-// |g| <= thr * sqrt(a b) or g = 0.  Returns whether a rotation is applied.
+// |g| <= thr * sqrt(a b) or g = 0.  For |zeta| > 1e100 (a rounding residue rotated against
+// a large column), t = 1 / (2|zeta|), which is exact to double precision and avoids the
+// overflow of 1 + zeta^2.  Returns whether a rotation is applied.
 __device__ inline bool jacobi_rotation(double a, double b, double gr, double gi, double thr,
                                        double& c, double& sr, double& si) {
   const double g2 = gr * gr + gi * gi;
@@ -135,7 +56,9 @@ __device__ inline bool jacobi_rotation(double a, double b, double gr, double gi,
   if (!(g2 > 0.0) || g2 <= thr * thr * fmax(a * b, 0.0)) return false;
   const double rg = rsqrt_f64(g2);  // 1 / |g|
   const double zeta = 0.5 * (b - a) * rg;
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_f64(fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double az = fabs(zeta);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) *
+                   (az > 1e100 ? 0.5 / az : rcp_f64(az + sqrt(1.0 + az * az)));
   c = rsqrt_f64(1.0 + t * t);
   const double sc = t * c * rg;
   sr = sc * gr;
@@ -433,13 +356,19 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   }
   __syncthreads();
 
-  // ---- convergence measure of this pair
+  // ---- convergence measure of this pair.  Pairs with a numerically zero column (norm
+  // below 16 u times its partner's, u the unit roundoff of T) do not count: their cosine is
+  // rounding noise left by an earlier cancellation, and rotating the residue against its
+  // partner sweep after sweep only shrinks it towards underflow.  tiny = (16 u)^2.  The
+  // inner rotations below do not use this test, so a pair the measure counts is always
+  // rotated.
+  constexpr double tiny = sizeof(T) == 4 ? 9.094947017729282e-13 : 3.1554436208840472e-30;
   double mx = 0.0;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
     if (i < j) {
       const double di = (double)G[i][i].re, dj = (double)G[j][j].re;
-      if (di > 0.0 && dj > 0.0)
+      if (fmin(di, dj) > tiny * fmax(di, dj))
         mx = fmax(mx, hypot((double)G[i][j].re, (double)G[i][j].im) / sqrt(di * dj));
     }
   }

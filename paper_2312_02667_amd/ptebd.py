@@ -29,7 +29,7 @@ FP32 = 1
 FLAG_NO_STABILIZE = 1
 FLAG_RELATIVE_EPS = 2
 FLAG_COMPLEMENT_EPS = 4
-FP32_CUTOFF_FLOOR = 1.1920928955078125e-07  # 2^-23, PTEBD_FP32_CUTOFF_FLOOR
+FP32_CUTOFF_FLOOR = 1.9073486328125e-06  # 2^-19, PTEBD_FP32_CUTOFF_FLOOR
 EPS_FLAGS = {"literal": 0, "relative": FLAG_RELATIVE_EPS, "complement": FLAG_COMPLEMENT_EPS}
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
@@ -52,7 +52,7 @@ class KernelStats(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-KERNELS = {"theta": 0, "jacobi": 1, "finalize": 2, "writeback": 3}
+KERNELS = {"theta": 0, "jacobi": 1, "finalize": 2, "writeback": 3, "sample": 4}
 
 
 class PtebdError(RuntimeError):
@@ -76,6 +76,9 @@ _SIGS = {
                                           ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_int, ctypes.POINTER(LayerStats)]),
     "ptebd_ptsu": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
+    "ptebd_canonicalize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp]),
+    "ptebd_sample": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp,
+                                     ctypes.POINTER(ctypes.c_uint8)]),
     "ptebd_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp]),
     "ptebd_overlap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_int, _dp, _dp]),
@@ -226,6 +229,23 @@ class MPS:
 
     def ptsu(self, steps: int, cutoff: float = 1e-12, s: int = 0):
         return _check(lib().ptebd_ptsu(self._h, s, int(steps), float(cutoff)))
+
+    def canonicalize(self, cutoff: float = 1e-12, s: int = 0) -> float:
+        """Canonical form with unit norm (in place); returns the norm before normalizing."""
+        out = ctypes.c_double()
+        _check(lib().ptebd_canonicalize(self._h, s, float(cutoff), ctypes.byref(out)))
+        return out.value
+
+    def sample(self, uniforms, s: int = 0) -> np.ndarray:
+        """Perfect sampling from a canonical state: one bit string (uint8 row) per row of
+        ``uniforms`` (shape (n_samples, N), values in [0, 1))."""
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        if u.ndim != 2 or u.shape[1] != self.n_sites[s]:
+            raise ValueError("uniforms must have shape (n_samples, n_sites)")
+        bits = np.zeros(u.shape, np.uint8)
+        _check(lib().ptebd_sample(self._h, s, int(u.shape[0]), _ptr(u, ctypes.c_double),
+                                  _ptr(bits, ctypes.c_uint8)), allow_warn=False)
+        return bits
 
     def _scalar(self, fn, s):
         out = ctypes.c_double()

@@ -7,9 +7,9 @@ import numpy as np
 from oracle import ptebd_oracle as po
 
 
-# The FP32 path drops sigma <= max(cutoff, 2^-23) sigma_1 (documented in include/ptebd.h);
+# The FP32 path drops sigma <= max(cutoff, 2^-19) sigma_1 (documented in include/ptebd.h);
 # the oracle is run with the same effective cutoff when it checks that path.
-FP32_CUTOFF_FLOOR = 2.0 ** -23
+FP32_CUTOFF_FLOOR = 2.0 ** -19
 
 
 def oracle_cutoff(cutoff: float, precision: str) -> float:

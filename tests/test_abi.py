@@ -85,4 +85,4 @@ def test_header_constants_match_binding():
     assert int(defs["PTEBD_FLAG_NO_STABILIZE"]) == ptebd.FLAG_NO_STABILIZE
     assert int(defs["PTEBD_FLAG_RELATIVE_EPS"]) == ptebd.FLAG_RELATIVE_EPS
     assert int(defs["PTEBD_FLAG_COMPLEMENT_EPS"]) == ptebd.FLAG_COMPLEMENT_EPS
-    assert float(defs["PTEBD_FP32_CUTOFF_FLOOR"]) == ptebd.FP32_CUTOFF_FLOOR == 2.0 ** -23
+    assert float(defs["PTEBD_FP32_CUTOFF_FLOOR"]) == ptebd.FP32_CUTOFF_FLOOR == 2.0 ** -19

@@ -112,3 +112,28 @@ def test_svd_haar_theta_full_size(precision):
         rec = (u[b] * s[b][None, :]) @ vh[b]
         assert np.linalg.norm(rec - a[b]) <= tol["rec"] * np.linalg.norm(a[b]) * 6
     say(f"  sweeps {list(sw)}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_svd_exactly_parallel_equal_columns(precision):
+    """Rank-one matrices whose nonzero columns are exactly parallel with exactly equal norms
+    (the two-site wavefunction between two singlet dimers).  The rotation that merges them
+    leaves a numerically zero column; the SVD must converge (no sweep cap) with finite
+    values, sigma = (|a|, 0, ...), instead of rotating that rounding residue until the
+    rotation angle overflows."""
+    u = np.array([1.0, 0.0, 0.0, -1.0]) / np.sqrt(2)
+    mats = [np.outer(u, np.array([1.0, 0.0, 0.0, 1.0]) / np.sqrt(2)),
+            np.outer(u, np.array([1.0, 0.0, 0.0, 1.0j]) / np.sqrt(2)),
+            np.outer(np.ones(8) / np.sqrt(8), np.ones(8) / np.sqrt(8)),
+            np.kron(np.eye(2), np.outer(u, u))]
+    for a in mats:
+        s, uu, vh, sw, code = ptebd.svd_batched(a.astype(np.complex128), precision)
+        say(f"parallel columns {a.shape} {precision}: sweeps {sw.tolist()}, sigma {np.round(s[0], 6).tolist()}")
+        assert code == 0
+        assert np.all(np.isfinite(s)) and np.all(np.isfinite(uu)) and np.all(np.isfinite(vh))
+        s_ref = np.linalg.svd(a, compute_uv=False)
+        assert np.max(np.abs(s[0] - s_ref)) <= (1e-14 if precision == "fp64" else 1e-6)
+        assert sw[0] <= 12  # residues are still orthogonalized among themselves: 9 FP64 sweeps measured at 8 x 8
+        r = int(np.sum(s_ref > 1e-8))
+        rec = (uu[0][:, :r] * s[0][:r]) @ vh[0][:r]
+        assert np.linalg.norm(rec - a) <= (1e-14 if precision == "fp64" else 1e-6)

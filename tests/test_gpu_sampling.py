@@ -1,0 +1,123 @@
+"""Canonicalize and perfect sampling on the GPU (the measurement step of Algorithm 1) against
+the oracle: Schmidt values, norm and canonical distance after ptebd_canonicalize, and the
+sampled bit strings for the same uniforms."""
+
+import numpy as np
+import pytest
+
+from oracle import ptebd_oracle as po
+from oracle import statevector as sv
+from paper_2312_02667_amd import circuits, inputs, ptebd
+from tests.gpu_util import lambda_diff, oracle_cutoff, say, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": {"lam": 1e-11, "norm": 1e-11, "canon": 1e-10, "tie": 1e-9},
+       "fp32": {"lam": 2e-5, "norm": 5e-5, "canon": 1e-4, "tie": 1e-4}}
+
+
+def _truncated_state(n, chi, depth, seed, precision, ptsu=0):
+    """A truncated (so not canonical) Haar-circuit state on the GPU, and the same state
+    exported to the oracle's form (the reference both sides start from)."""
+    layers = inputs.brickwork_circuit(n, depth, seed)
+    m = ptebd.MPS(n, chi, precision)
+    for bonds, gates in layers:
+        m.apply_layer(bonds, gates, chi_max=chi, ptsu_steps=ptsu)
+    return m, to_oracle(m)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,chi,depth", [(12, 8, 10), (40, 32, 14), (2, 2, 3)])
+def test_canonicalize_matches_oracle(precision, n, chi, depth):
+    """A truncated (non-canonical) Haar-circuit state: after canonicalize, Schmidt values equal
+    the oracle's sequential-SVD canonicalization of the same (exported) state, the state is the
+    same up to its norm, and the canonical distance (Eq. (dist_to_cano)) vanishes."""
+    tol = TOL[precision]
+    m, ref = _truncated_state(n, chi, depth, 1, precision)
+    before = po.norm(ref)
+    snap = ptebd.MPS(n, chi, precision)
+    g, l = m.export()
+    snap.import_state(g, l)
+    say(f"canonicalize N={n} chi={chi} {precision}: C before {m.canon_distance():.3e}")
+    nrm = m.canonicalize(cutoff=1e-12)
+    can, nrm_ref = po.canonicalize(ref, cutoff=oracle_cutoff(1e-12, precision))
+    say(f"  norm {nrm:.12f} (oracle {nrm_ref:.12f}), C after {m.canon_distance():.3e}")
+    assert abs(nrm - nrm_ref) <= tol["norm"] * nrm_ref
+    assert abs(nrm_ref - before) <= 1e-10 * before
+    got = to_oracle(m)
+    assert got.bond_dims() == can.bond_dims()
+    assert lambda_diff(got, can) <= tol["lam"]
+    assert abs(m.norm() - 1.0) <= tol["norm"]
+    assert m.canon_distance() <= tol["canon"]
+    # the same state: |<before|after>| = norm before
+    assert abs(abs(m.overlap(snap)) - nrm) <= tol["norm"] * nrm
+    m.close()
+    snap.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,chi,depth,n_samples", [(10, 8, 8, 500), (48, 32, 14, 256)])
+def test_sampling_matches_oracle(precision, n, chi, depth, n_samples):
+    """Same uniforms on both sides: identical bit strings, except for samples whose path
+    passes a decision within rounding of its threshold (counted, and required to be rare)."""
+    tol = TOL[precision]
+    m, ref = _truncated_state(n, chi, depth, 2, precision)
+    m.canonicalize(cutoff=1e-12)
+    can, _ = po.canonicalize(ref, cutoff=oracle_cutoff(1e-12, precision))
+    rng = np.random.default_rng(1000 + n)
+    u = rng.random((n_samples, n))
+    say(f"sample N={n} chi={chi} S={n_samples} {precision}")
+    got = m.sample(u)
+    want, margin = po.sample(can, u, return_margins=True)
+    close = margin < tol["tie"]
+    mismatch = np.any(got != want, axis=1)
+    say(f"  mismatches {int(mismatch.sum())}, near-ties {int(close.sum())}")
+    assert not np.any(mismatch & ~close)
+    # a decision lands within the window with probability 2 * tie: expect about
+    # 2 * tie * N per sample; the bound leaves room for 5x that plus a few
+    assert close.sum() <= 5 * 2 * tol["tie"] * n * n_samples + 3
+    m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sampling_frequencies_against_state_vector(precision):
+    """N = 6 exact circuit: outcome frequencies of 40000 GPU samples within 5 standard
+    deviations of |psi|^2 (Born's rule), and the PQC singlet product samples anti-aligned
+    pairs only."""
+    n = 6
+    layers = inputs.brickwork_circuit(n, 6, 4, special=False)
+    m = ptebd.MPS(n, 16, precision)
+    for bonds, gates in layers:
+        m.apply_layer(bonds, gates, chi_max=16)
+    m.canonicalize()
+    psi = sv.run_circuit(n, layers)
+    prob = np.abs(psi) ** 2
+    s = 40000
+    bits = m.sample(np.random.default_rng(77).random((s, n)))
+    idx = bits.astype(np.int64) @ (1 << np.arange(n - 1, -1, -1))
+    freq = np.bincount(idx, minlength=2 ** n) / s
+    assert np.all(np.abs(freq - prob) <= 5 * np.sqrt(prob * (1 - prob) / s) + 1e-12)
+    m.close()
+    # singlet dimers on (0,1),(2,3),(4,5): every pair of bits is 01 or 10
+    d = ptebd.MPS(n, 4, precision)
+    b, g = circuits.pqc_1d(n, 0, seed=0)[0]
+    d.apply_layer(b, g, chi_max=4)
+    d.canonicalize()
+    bits = d.sample(np.random.default_rng(78).random((2000, n)))
+    assert np.all(bits[:, 0::2] != bits[:, 1::2])
+    assert abs(bits[:, 0].mean() - 0.5) < 0.05
+    d.close()
+
+
+def test_sample_argument_errors():
+    m = ptebd.MPS(4, 4, "fp64")
+    m.canonicalize()
+    with pytest.raises(ptebd.PtebdError):
+        m.sample(np.full((3, 4), 1.0))
+    with pytest.raises(ptebd.PtebdError):
+        m.sample(np.full((3, 4), np.nan))
+    with pytest.raises(ValueError):
+        m.sample(np.zeros((3, 5)))
+    assert m.sample(np.zeros((0, 4))).shape == (0, 4)
+    assert np.all(m.sample(np.zeros((5, 4))) == 0)      # |0000>
+    m.close()
