@@ -53,6 +53,8 @@ def parse_args(argv=None):
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-f1", action="store_true",
+                   help="skip the canonicalize + sampling measurement")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU seconds for the oracle sample")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -179,6 +181,43 @@ def cpu_baseline(chi: int, seconds: float):
                       f"Vidal state, {el:.1f} s"}
 
 
+def measure_f1(precision: str, n_sites: int, chi: int, depth: int, n_samples: int, seed: int):
+    """The measurement step after the last layer (Algorithm 1): canonicalize a truncated
+    Haar-circuit state, then draw n_samples bit strings by perfect sampling.  Returns wall
+    times and the sampling kernel's achieved rate (algorithmic flops / event time)."""
+    import torch
+
+    from paper_2312_02667_amd import inputs, ptebd
+
+    layers = inputs.brickwork_circuit(n_sites, depth, seed)
+    m = ptebd.MPS(n_sites, chi, precision)
+    for bonds, gates in layers:
+        m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nrm = m.canonicalize(cutoff=1e-12)
+    t_can = time.perf_counter() - t0
+    u = np.random.default_rng(seed + 1).random((n_samples, n_sites))
+    m.sample(u[:16])                      # warm-up (buffers, code objects)
+    m.set_profiling(True)
+    t0 = time.perf_counter()
+    bits = m.sample(u)
+    t_samp = time.perf_counter() - t0
+    ks = m.kernel_stats()["sample"]
+    m.set_profiling(False)
+    m.close()
+    peak = PEAKS_TFLOPS[precision]
+    ach = ks["flops"] / (ks["total_ms"] / 1e3) / 1e12 if ks["total_ms"] > 0 else 0.0
+    return {"workload": f"N={n_sites} chi_max={chi} Haar SU(4) brickwork depth {depth}, "
+                        f"then canonicalize and {n_samples} samples",
+            "canonicalize_s": t_can, "norm_before": nrm,
+            "sample_s": t_samp, "samples_per_s": n_samples / t_samp,
+            "sample_kernel_ms": ks["total_ms"], "sample_launches": ks["launches"],
+            "sample_roofline": {"bound": "mfma", "achieved": ach, "peak": peak,
+                                "unit": "TFLOP/s", "frac": ach / peak},
+            "mean_bit": float(bits.mean())}
+
+
 def main(argv=None):
     args = parse_args(argv)
     if args.gpus != 1:
@@ -241,6 +280,9 @@ def main(argv=None):
         result["err_F_vs_fp64_gpu"] = err_f
         log(f"err_F(mixed vs fp64) = {err_f:.3e}")
         f64_m.close()
+    if not args.no_f1:
+        log("measurement step: canonicalize + perfect sampling (N=100, chi=64) ...")
+        result["f1"] = measure_f1(args.precision, 100, 64, 20, 8192, args.seed)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample) ...")
         result["cpu_baseline"] = cpu_baseline(chi, args.cpu_seconds)
