@@ -124,9 +124,14 @@ int ptebd_mps_destroy(ptebd_mps_t h);
  * |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit roundoff of the
  * precision; default 4); inner_sweeps in [1, 64], the cyclic sweeps over each 32x32 block
  * pair's Gram matrix (default 2 for FP32, 1 for FP64); sort_pairs 0/1, order each pair's
- * new columns by norm (default 1). */
+ * new columns by norm (default 1); precondition 0/1 (FP32 handles only, default 1): sort
+ * theta's columns by norm, factor their FP64 Gram matrix G = R^H R (Cholesky) and run the
+ * Jacobi on R^H, whose columns start nearly orthogonal, with the left vectors recovered as
+ * theta Y / S (about half the sweeps on saturated Haar bonds, and no right-vector
+ * accumulation).  FP64 handles ignore it: the Gram matrix would square the condition
+ * number and cost the relative accuracy of the FP64 path. */
 int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int inner_sweeps,
-                         int sort_pairs);
+                         int sort_pairs, int precondition);
 
 /*
  * Apply one circuit layer (one step of Algorithm 1) to states of the batch.
@@ -268,7 +273,9 @@ int ptebd_svd_batched(int precision, int batch, int m, int n, const double* a, d
 #define PTEBD_KERNEL_FINALIZE 2
 #define PTEBD_KERNEL_WRITEBACK 3
 #define PTEBD_KERNEL_SAMPLE 4   /* ptebd_sample: one launch per site */
-#define PTEBD_KERNEL_COUNT 5
+#define PTEBD_KERNEL_PRECOND 5  /* FP32 preconditioning: column sort, FP64 Gram, Cholesky,
+                                   X = R^H, and the recovery of the singular vectors */
+#define PTEBD_KERNEL_COUNT 6
 
 typedef struct {
   double total_ms;   /* summed event-measured duration of the launches */

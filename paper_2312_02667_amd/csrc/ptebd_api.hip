@@ -193,6 +193,7 @@ struct ptebd_mps {
   double tol_factor = 4.0;
   int inner_sweeps = 1;
   int sort_pairs = 1;
+  int precondition = 1;  // FP32 handles only
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   char* gamma_slot(int s, int q) const {
@@ -209,7 +210,7 @@ namespace {
 
 // Layout of the per-gate output block inside outbuf.
 struct OutLayout {
-  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, work, total;
+  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, work, ps, gmax, total;
 };
 
 OutLayout out_layout(int n, int cmax) {
@@ -231,6 +232,8 @@ OutLayout out_layout(int n, int cmax) {
   L.offbits = take(sizeof(uint32_t) * n);
   L.counters = take(sizeof(int32_t) * 4);
   L.work = take(sizeof(unsigned long long) * 4);
+  L.ps = take(sizeof(int32_t) * (size_t)n * cmax);
+  L.gmax = take(sizeof(double) * n);
   L.total = off;
   return L;
 }
@@ -298,9 +301,12 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
   if (n == 0) return PTEBD_OK;
   if (n > 65535) return fail(PTEBD_EINVAL, "too many bond updates in one batch (max 65535)");
 
-  std::vector<size_t> woff(n), voff(n);
+  // The FP32 path preconditions the SVD (column sort, FP64 Gram, Cholesky, Jacobi on R^H);
+  // its per-gate workspace adds the Gram matrix (C x C complex FP64) and U S (R x C).
+  const bool pre = sizeof(T) == 4 && h->precondition;
+  std::vector<size_t> woff(n), voff(n), goff(n), loff(n);
   size_t total = 0;
-  int max_c = 1, max_tiles = 1, cmax = 1;
+  int max_c = 1, max_r = 1, max_tiles = 1, cmax = 1;
   std::vector<GateDesc> descs(n);
   for (int i = 0; i < n; ++i) {
     const StateInfo& si = h->st[items[i].s];
@@ -324,16 +330,25 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
     total += (size_t)d.R * d.C;
     voff[i] = total;
     total += (size_t)d.C * d.C;
+    if (pre) {
+      total += total & 1;  // the complex FP64 Gram matrix is 16-byte aligned
+      goff[i] = total;
+      total += 2 * (size_t)d.C * d.C;
+      loff[i] = total;
+      total += (size_t)d.R * d.C;
+    }
     max_c = std::max(max_c, d.C);
+    max_r = std::max(max_r, d.R);
     cmax = std::max(cmax, d.C);
     max_tiles = std::max(max_tiles, ((d.cl + 31) / 32) * ((d.cr + 31) / 32));
   }
   const OutLayout L = out_layout(n, cmax);
   PT_CHECK(h->work.ensure(total * sizeof(cplx<T>)));
-  PT_CHECK(h->desc.ensure(sizeof(GateDesc) * n));
+  const int ndesc = pre ? 3 * n : n;  // theta, Jacobi and write-back descriptors
+  PT_CHECK(h->desc.ensure(sizeof(GateDesc) * ndesc));
   PT_CHECK(h->gates.ensure(sizeof(double) * 32 * n));
   PT_CHECK(h->outbuf.ensure(L.total));
-  PT_CHECK(h->h_desc.ensure(sizeof(GateDesc) * n));
+  PT_CHECK(h->h_desc.ensure(sizeof(GateDesc) * ndesc));
   PT_CHECK(h->h_gates.ensure(sizeof(double) * 32 * n));
   PT_CHECK(h->h_out.ensure(L.total));
   PT_CHECK(h->h_small.ensure(64));
@@ -350,6 +365,8 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
     d.lam_r = h->lam_slot(s, q + 2);
     d.w = wbase + woff[i] * sizeof(cplx<T>);
     d.v = wbase + voff[i] * sizeof(cplx<T>);
+    d.gram = pre ? wbase + goff[i] * sizeof(cplx<T>) : nullptr;
+    d.left = pre ? wbase + loff[i] * sizeof(cplx<T>) : nullptr;
     if (items[i].gate) {
       std::memcpy(hg + 32 * i, items[i].gate, 32 * sizeof(double));
       d.gate = (const double*)h->gates.p + 32 * i;
@@ -358,26 +375,59 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
     }
   }
   std::memcpy(h->h_desc.p, descs.data(), sizeof(GateDesc) * n);
+  if (pre) {
+    // Jacobi on X = R^H (C x C, in the V slot, no right vectors kept); write-back from
+    // U S (left) and the right vectors (stored in the Gram buffer)
+    GateDesc* jd = (GateDesc*)h->h_desc.p + n;
+    GateDesc* wd = (GateDesc*)h->h_desc.p + 2 * n;
+    for (int i = 0; i < n; ++i) {
+      jd[i] = descs[i];
+      jd[i].w = descs[i].v;
+      jd[i].v = nullptr;
+      jd[i].R = descs[i].C;
+      wd[i] = descs[i];
+      wd[i].w = descs[i].left;
+      wd[i].v = descs[i].gram;
+    }
+  }
   hipStream_t stream = h->stream;
-  PT_HIP(hipMemcpyAsync(h->desc.p, h->h_desc.p, sizeof(GateDesc) * n, hipMemcpyHostToDevice,
+  PT_HIP(hipMemcpyAsync(h->desc.p, h->h_desc.p, sizeof(GateDesc) * ndesc, hipMemcpyHostToDevice,
                         stream));
   PT_HIP(hipMemcpyAsync(h->gates.p, h->h_gates.p, sizeof(double) * 32 * n, hipMemcpyHostToDevice,
                         stream));
   const GateDesc* d_desc = (const GateDesc*)h->desc.p;
+  const GateDesc* d_jdesc = pre ? d_desc + n : d_desc;
+  const GateDesc* d_wdesc = pre ? d_desc + 2 * n : d_desc;
   const LayerOut lo = make_layer_out(h->outbuf.p, L, cmax);
+  ptebd::PrecondOut po;
+  po.ps = (int32_t*)((char*)h->outbuf.p + L.ps);
+  po.gmax = (double*)((char*)h->outbuf.p + L.gmax);
+  po.cmax = cmax;
 
   Prof* pf = &h->prof;
   timed(pf, PTEBD_KERNEL_THETA, stream, [&] { ptebd::launch_theta<T>(d_desc, n, max_tiles, stream); });
   PT_HIP(hipGetLastError());
+  if (pre)
+    timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
+      ptebd::launch_colsort(d_desc, n, po, stream);
+      ptebd::launch_gram64(d_desc, n, max_c, po, stream);
+      ptebd::launch_cholesky(d_desc, n, max_c, po, stream);
+      ptebd::launch_xinit(d_jdesc, n, max_c, stream);
+    });
+  PT_HIP(hipGetLastError());
   int n_unconv = 0;
-  PT_CHECK(run_jacobi<T>(stream, d_desc, n, max_c, lo, h->precision, h->max_sweeps,
+  PT_CHECK(run_jacobi<T>(stream, d_jdesc, n, max_c, lo, h->precision, h->max_sweeps,
                          h->tol_factor, h->inner_sweeps, h->sort_pairs, (int32_t*)h->h_small.p,
                          &n_unconv, pf));
-  timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_desc, n, cutoff, lo, stream); });
-  timed(pf, PTEBD_KERNEL_WRITEBACK, stream, [&] { ptebd::launch_writeback<T>(d_desc, n, lo, stream); });
+  timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_jdesc, n, cutoff, lo, stream); });
+  if (pre)
+    timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
+      ptebd::launch_recover(d_desc, d_jdesc, n, max_r, max_c, po, lo, stream);
+    });
+  timed(pf, PTEBD_KERNEL_WRITEBACK, stream, [&] { ptebd::launch_writeback<T>(d_wdesc, n, lo, stream); });
   PT_HIP(hipGetLastError());
   // copy back the small per-gate outputs (k .. counters are contiguous after perm)
-  PT_HIP(hipMemcpyAsync((char*)h->h_out.p + L.k, (char*)h->outbuf.p + L.k, L.total - L.k,
+  PT_HIP(hipMemcpyAsync((char*)h->h_out.p + L.k, (char*)h->outbuf.p + L.k, L.ps - L.k,
                         hipMemcpyDeviceToHost, stream));
   PT_HIP(hipStreamSynchronize(stream));
   const char* ho = (const char*)h->h_out.p;
@@ -408,8 +458,14 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
       const double cl = d.cl, cm = d.cm, cr = d.cr, kk = hk[i];
       pf->st[PTEBD_KERNEL_THETA].flops += 32.0 * cl * cm * cr + (d.has_gate ? 128.0 * cl * cr : 0.0);
       pf->st[PTEBD_KERNEL_THETA].bytes += ce * (2.0 * cl * cm + 2.0 * cm * cr + 4.0 * cl * cr);
-      pf->st[PTEBD_KERNEL_FINALIZE].bytes += ce * (double)d.R * d.C;
+      pf->st[PTEBD_KERNEL_FINALIZE].bytes += ce * (double)(pre ? d.C : d.R) * d.C;
       pf->st[PTEBD_KERNEL_WRITEBACK].bytes += ce * 4.0 * kk * (cl + cr);
+      if (pre) {
+        // upper-tile FP64 Gram 4 R C^2, Cholesky 8 C^3 / 3, U S = W Yhat 8 R C k
+        const double R = d.R, C = d.C;
+        pf->st[PTEBD_KERNEL_PRECOND].flops += 4.0 * R * C * C + 8.0 * C * C * C / 3.0 + 8.0 * R * C * kk;
+        pf->st[PTEBD_KERNEL_PRECOND].bytes += ce * (3.0 * R * C + 6.0 * C * C + R * kk);
+      }
     }
   }
   if (hc[2] & 1) return fail(PTEBD_EANNIHILATED, "a two-site wavefunction vanished or eps >= 1");
@@ -614,16 +670,18 @@ int ptebd_mps_destroy(ptebd_mps_t h) {
 }
 
 int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int inner_sweeps,
-                         int sort_pairs) {
+                         int sort_pairs, int precondition) {
   PT_CHECK(check_handle(h));
   if (max_sweeps < 1 || !(tol_factor > 0.0) || !std::isfinite(tol_factor) || inner_sweeps < 1 ||
-      inner_sweeps > 64 || (sort_pairs != 0 && sort_pairs != 1))
-    return fail(PTEBD_EINVAL,
-                "need max_sweeps >= 1, tol_factor > 0, inner_sweeps in [1, 64], sort_pairs 0/1");
+      inner_sweeps > 64 || (sort_pairs != 0 && sort_pairs != 1) ||
+      (precondition != 0 && precondition != 1))
+    return fail(PTEBD_EINVAL, "need max_sweeps >= 1, tol_factor > 0, inner_sweeps in [1, 64], "
+                              "sort_pairs and precondition 0/1");
   h->max_sweeps = max_sweeps;
   h->tol_factor = tol_factor;
   h->inner_sweeps = inner_sweeps;
   h->sort_pairs = sort_pairs;
+  h->precondition = precondition;
   return PTEBD_OK;
 }
 

@@ -38,8 +38,18 @@ struct GateDesc {
   double* lam_m;           // Lambda[q+1] (written: k values)
   const double* lam_r;     // Lambda[q+2] (cr)
   void* w;                 // R x C work matrix (complex T)
-  void* v;                 // C x C rotation matrix (complex T)
+  void* v;                 // C x C rotation matrix (complex T), or nullptr: not accumulated
   const double* gate;      // 16 complex128, U[(s' t'), (s t)] row-major
+  void* gram;              // preconditioned FP32 path: C x C complex FP64 (G, then R, then
+                           // the right vectors as complex FP32), else nullptr
+  void* left;              // preconditioned FP32 path: R x C complex FP32 (U S), else nullptr
+};
+
+// Per-gate side data of the preconditioned SVD (ptebd_precond.hip).
+struct PrecondOut {
+  int32_t* ps;       // column order of W by descending norm, n_gates * cmax
+  double* gmax;      // largest column norm^2 of W, per gate
+  int32_t cmax;
 };
 
 // Per-gate outputs of a layer's SVD + truncation, device arrays of length n_gates
@@ -101,6 +111,19 @@ void launch_finalize(const GateDesc* d_desc, int n_gates, double cutoff, const L
 template <class T>
 void launch_writeback(const GateDesc* d_desc, int n_gates, const LayerOut& out,
                       hipStream_t stream);
+
+// Preconditioned SVD of the FP32 path (ptebd_precond.hip).  d_desc: the theta descriptors
+// (w = theta, gram, left set); d_jdesc: the Jacobi descriptors (w = X, v = nullptr, R = C,
+// gram as in d_desc).
+void launch_colsort(const GateDesc* d_desc, int n_gates, const PrecondOut& po,
+                    hipStream_t stream);
+void launch_gram64(const GateDesc* d_desc, int n_gates, int max_c, const PrecondOut& po,
+                   hipStream_t stream);
+void launch_cholesky(const GateDesc* d_desc, int n_gates, int max_c, const PrecondOut& po,
+                     hipStream_t stream);
+void launch_xinit(const GateDesc* d_jdesc, int n_gates, int max_c, hipStream_t stream);
+void launch_recover(const GateDesc* d_desc, const GateDesc* d_jdesc, int n_gates, int max_r,
+                    int max_c, const PrecondOut& po, const LayerOut& out, hipStream_t stream);
 
 // Sampling and normalization kernels (ptebd_sample.hip).
 template <class T>

@@ -200,7 +200,7 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
   const GateDesc* d = descs + g;
   const int C = d->C;
   cplx<T>* v = (cplx<T>*)d->v;
-  const size_t total = (size_t)C * C;
+  const size_t total = v != nullptr ? (size_t)C * C : 0;  // no V: right vectors not kept
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const size_t col = e / C, row = e % C;
@@ -225,11 +225,13 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
 // blocks of one gate's W, forms the 32x32 Gram matrix G = W_IJ^H W_IJ on MFMA, records the
 // largest relative off-diagonal |G_ij| / sqrt(G_ii G_jj), runs cyclic Jacobi sweeps on G
 // (rotation angles computed in FP64; G and the accumulated rotation Q held in the path's
-// precision T) and applies Q to the 32 columns of W and of V on MFMA.  Pairs of one round
-// are disjoint, so no two workgroups of a gate touch the same column.
+// precision T) and applies Q to the 32 columns of W and, when the descriptor has one, of V
+// on MFMA.  Pairs of one round are disjoint, so no two workgroups of a gate touch the same
+// column.
 //
-// LDS: G and Q only (2 x 32 x 33 complex T); the cross-wave reduction of the Gram tiles and
-// the T copy of Q used by the column update alias them.
+// LDS: G and Q with their next-round copies (4 x 32 x 33 complex T); the cross-wave
+// reduction of the Gram tiles and the permuted copy of Q used by the column update alias
+// them.
 template <class T>
 __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
                                                            int round, int nbp, LayerOut out,
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     atomicAdd(&out.work[0], (unsigned long long)R);
     atomicAdd(&out.work[2], 1ull);
     if (rotate) {
-      atomicAdd(&out.work[1], (unsigned long long)(R + C));
+      atomicAdd(&out.work[1], (unsigned long long)(R + (V != nullptr ? C : 0)));
       atomicAdd(&out.work[3], 1ull);
     }
   }
@@ -514,7 +516,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
 
   // ---- column update [W_I W_J] <- [W_I W_J] Q and [V_I V_J] <- [V_I V_J] Q on MFMA,
   // next 16-row chunk prefetched
-  for (int pass = 0; pass < 2; ++pass) {
+  const int npass = V != nullptr ? 2 : 1;
+  for (int pass = 0; pass < npass; ++pass) {
     cplx<T>* __restrict__ M = pass == 0 ? W : V;
     const int rows = pass == 0 ? R : C;
     cplx<T> av[8], an[8];

@@ -1,0 +1,454 @@
+// Preconditioning of the SVD on the mixed (FP32) path, one batch of gates per launch.
+//
+// For the work matrix W (R x C, R >= C; theta or theta^H):
+//   colsort_kernel   -- column norms of W in FP64 and a permutation ps sorting them in
+//                       descending order (A = W P, A[:, i] = W[:, ps[i]])
+//   gram64_kernel    -- G = A^H A in FP64 on MFMA (upper 32x32 tiles)
+//   potrf / trsm / herk_kernel -- blocked Cholesky G = R^H R (R upper), in place, FP64;
+//                       a pivot at or below 1e-13 G_00 marks a numerically dependent column
+//                       (its row of R is set to zero)
+//   xinit_kernel     -- X = R^H in FP32: the one-sided Jacobi then runs on X instead of W
+//   recover_kernel   -- after the Jacobi (X Q = Y S, no V kept): the right vectors of W,
+//                       Yhat[ps[i], j] = X[i, j] / ||X[:, j]||, and W Yhat = U S
+// A = Q R with Q = A R^{-1} unitary, so R, and X = R^H, carry the singular values of W, and
+// if X's columns after the rotations are Y S (Y orthonormal) then A = (A Y S^{-1}) S Y^H:
+// right vectors P Y, left vectors W (P Y) / S.  Sorting the columns by norm first makes R
+// graded, which halves the number of Jacobi sweeps on the saturated theta of a Haar layer.
+// The Gram matrix squares the condition number: in FP64 it resolves every singular value
+// above ~1e-7 sigma_1 of FP32 data to well below the FP32 rounding of theta, which is why the
+// FP64 path does not use it.
+#include <algorithm>
+
+#include "ptebd_device.h"
+#include "ptebd_internal.h"
+
+namespace ptebd {
+namespace {
+
+typedef cplx<double> z64;
+typedef cplx<float> z32;
+
+// ---------------------------------------------------------------- column sort
+// One workgroup per gate: column norms^2 of W (C <= 1024), bitonic sort, descending (ties
+// by index).  Writes ps[0..C) and the largest norm^2 (the Cholesky pivot scale).
+__global__ __launch_bounds__(256) void colsort_kernel(const GateDesc* __restrict__ descs,
+                                                      PrecondOut po) {
+  const int g = blockIdx.x;
+  const GateDesc* d = descs + g;
+  const int R = d->R, C = d->C;
+  const z32* __restrict__ W = (const z32*)d->w;
+  __shared__ double key[1024];
+  __shared__ int idx[1024];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int P = 1;
+  while (P < C) P <<= 1;
+  for (int c = wave; c < C; c += 4) {
+    double acc = 0.0;
+    for (int r = lane; r < R; r += 64) {
+      const z32 z = W[(size_t)c * R + r];
+      acc += (double)z.re * z.re + (double)z.im * z.im;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      key[c] = acc;
+      idx[c] = c;
+    }
+  }
+  for (int c = C + tid; c < P; c += 256) {
+    key[c] = -1.0;
+    idx[c] = c;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < (P >> 1); i += 256) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool descending = (lo & size) == 0;
+        const double klo = key[lo], khi = key[hi];
+        const int ilo = idx[lo], ihi = idx[hi];
+        // descending by key, ascending index among equal keys
+        const bool lo_first = klo > khi || (klo == khi && ilo < ihi);
+        if (descending ? !lo_first : lo_first) {
+          key[lo] = khi;
+          key[hi] = klo;
+          idx[lo] = ihi;
+          idx[hi] = ilo;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  int* ps = po.ps + (size_t)g * po.cmax;
+  for (int c = tid; c < C; c += 256) ps[c] = idx[c];
+  if (tid == 0) po.gmax[g] = key[0];
+}
+
+// ---------------------------------------------------------------- Gram matrix
+// G[i, j] = sum_r conj(W[r, ps[i]]) W[r, ps[j]] in FP64 for the upper 32x32 tiles
+// (ti <= tj); column-major C x C.  Four waves, each a 16x16 sub-tile; rows in steps of 4.
+__device__ inline void tile_of(int t, int nt, int& ti, int& tj) {
+  // upper-triangular tile t (row-major over ti, tj >= ti)
+  ti = 0;
+  int rowlen = nt;
+  while (t >= rowlen) {
+    t -= rowlen;
+    ++ti;
+    --rowlen;
+  }
+  tj = ti + t;
+}
+
+__global__ __launch_bounds__(256) void gram64_kernel(const GateDesc* __restrict__ descs,
+                                                     PrecondOut po) {
+  const int g = blockIdx.y;
+  const GateDesc* d = descs + g;
+  const int R = d->R, C = d->C;
+  const int nt = (C + 31) >> 5;
+  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  int ti, tj;
+  tile_of(blockIdx.x, nt, ti, tj);
+  const z32* __restrict__ W = (const z32*)d->w;
+  const int* __restrict__ ps = po.ps + (size_t)g * po.cmax;
+  z64* __restrict__ G = (z64*)d->gram;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int i0 = ti * 32 + (wave >> 1) * 16, j0 = tj * 32 + (wave & 1) * 16;
+  const int ci = i0 + col, cj = j0 + col;
+  const bool oki = ci < C, okj = cj < C;
+  const z32* __restrict__ wi = W + (size_t)(oki ? ps[ci] : 0) * R;
+  const z32* __restrict__ wj = W + (size_t)(okj ? ps[cj] : 0) * R;
+  typedef Mfma<double>::v4 V4;
+  V4 acc[2];
+  for (int v = 0; v < 4; ++v) {
+    acc[0][v] = 0.0;
+    acc[1][v] = 0.0;
+  }
+  for (int r0 = 0; r0 < R; r0 += 4) {
+    const int r = r0 + grp;
+    z64 x, y;
+    x.re = x.im = y.re = y.im = 0.0;
+    if (r < R) {
+      if (oki) {
+        const z32 a = wi[r];
+        x.re = a.re;
+        x.im = a.im;
+      }
+      if (okj) {
+        const z32 b = wj[r];
+        y.re = b.re;
+        y.im = b.im;
+      }
+    }
+    gram_mfma<double>(acc, x, y);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + Mfma<double>::row(lane, v), j = j0 + col;
+    if (i < C && j < C) {
+      z64 z;
+      z.re = acc[0][v];
+      z.im = acc[1][v];
+      G[(size_t)j * C + i] = z;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- blocked Cholesky
+// G = R^H R with R upper triangular, overwriting the upper triangle of G, 32 columns per
+// block step kb: potrf factors the diagonal block, trsm solves the block row
+// R[kb, j] = R[kb, kb]^{-H} G[kb, j], herk updates the trailing upper tiles
+// G[i, j] -= R[kb, i]^H R[kb, j].  A pivot d <= 1e-13 * G_00 (G_00 the largest column
+// norm^2, the columns being sorted) is a numerically dependent column: its row of R is zero.
+constexpr double kPivotTol = 1e-13;
+
+__global__ __launch_bounds__(256) void potrf_kernel(const GateDesc* __restrict__ descs,
+                                                    PrecondOut po, int kb) {
+  const int g = blockIdx.x;
+  const int C = descs[g].C;
+  const int b0 = kb * 32;
+  if (b0 >= C) return;
+  const int nb = min(32, C - b0);
+  z64* __restrict__ G = (z64*)descs[g].gram;
+  const double thr = kPivotTol * po.gmax[g];
+  __shared__ z64 A[32][33];
+  __shared__ double piv;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e & 31, j = e >> 5;
+    z64 z;
+    z.re = z.im = 0.0;
+    if (i < nb && j < nb && i <= j) z = G[(size_t)(b0 + j) * C + b0 + i];
+    A[i][j] = z;
+  }
+  __syncthreads();
+  for (int p = 0; p < nb; ++p) {
+    if (tid == 0) {
+      const double dv = A[p][p].re;
+      piv = dv > thr ? sqrt(dv) : 0.0;
+    }
+    __syncthreads();
+    const double rp = piv;
+    // row p of R: R[p][l] = A[p][l] / R[p][p] for l > p (zero row for a dropped pivot)
+    if (tid < 32) {
+      const int l = tid;
+      if (l == p) {
+        A[p][p].re = rp;
+        A[p][p].im = 0.0;
+      } else if (l > p && l < nb) {
+        if (rp > 0.0) {
+          A[p][l].re /= rp;
+          A[p][l].im /= rp;
+        } else {
+          A[p][l].re = 0.0;
+          A[p][l].im = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    // trailing: A[l][m] -= conj(R[p][l]) R[p][m], p < l <= m
+    for (int e = tid; e < 1024; e += 256) {
+      const int l = e & 31, m = e >> 5;
+      if (l > p && l <= m && m < nb) {
+        const z64 a = A[p][l], b = A[p][m];
+        A[l][m].re -= a.re * b.re + a.im * b.im;
+        A[l][m].im -= a.re * b.im - a.im * b.re;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e & 31, j = e >> 5;
+    if (i < nb && j < nb && i <= j) G[(size_t)(b0 + j) * C + b0 + i] = A[i][j];
+  }
+}
+
+// Block row: X = R_kk^{-H} G[kb, j] for the tiles j > kb (blockIdx.x + kb + 1), forward
+// substitution with the lower-triangular R_kk^H; one thread per column of the tile.
+__global__ __launch_bounds__(256) void trsm_kernel(const GateDesc* __restrict__ descs,
+                                                   int kb) {
+  const int g = blockIdx.y;
+  const int C = descs[g].C;
+  const int b0 = kb * 32;
+  const int c0 = (kb + 1 + blockIdx.x) * 32;
+  if (c0 >= C) return;
+  const int nb = min(32, C - b0), nc = min(32, C - c0);
+  z64* __restrict__ G = (z64*)descs[g].gram;
+  __shared__ z64 Rk[32][33];
+  __shared__ z64 X[32][33];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e & 31, j = e >> 5;
+    z64 z;
+    z.re = z.im = 0.0;
+    if (i < nb && j < nb && i <= j) z = G[(size_t)(b0 + j) * C + b0 + i];
+    Rk[i][j] = z;
+    z64 x;
+    x.re = x.im = 0.0;
+    if (i < nb && j < nc) x = G[(size_t)(c0 + j) * C + b0 + i];
+    X[i][j] = x;
+  }
+  __syncthreads();
+  if (tid < 32 && tid < nc) {
+    const int j = tid;
+    for (int i = 0; i < nb; ++i) {
+      // X[i][j] = (X[i][j] - sum_{l<i} conj(Rk[l][i]) X[l][j]) / Rk[i][i]
+      double re = X[i][j].re, im = X[i][j].im;
+      for (int l = 0; l < i; ++l) {
+        const z64 r = Rk[l][i], x = X[l][j];
+        re -= r.re * x.re + r.im * x.im;
+        im -= r.re * x.im - r.im * x.re;
+      }
+      const double rii = Rk[i][i].re;
+      X[i][j].re = rii > 0.0 ? re / rii : 0.0;
+      X[i][j].im = rii > 0.0 ? im / rii : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e & 31, j = e >> 5;
+    if (i < nb && j < nc) G[(size_t)(c0 + j) * C + b0 + i] = X[i][j];
+  }
+}
+
+// Trailing update of the upper tiles (ti, tj), kb < ti <= tj: G -= R[kb, ti]^H R[kb, tj].
+__global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ descs,
+                                                   int kb) {
+  const int g = blockIdx.y;
+  const int C = descs[g].C;
+  const int nt = (C + 31) >> 5;
+  const int nrem = nt - kb - 1;
+  if (nrem <= 0 || (int)blockIdx.x >= nrem * (nrem + 1) / 2) return;
+  int ti, tj;
+  tile_of(blockIdx.x, nrem, ti, tj);
+  ti += kb + 1;
+  tj += kb + 1;
+  z64* __restrict__ G = (z64*)descs[g].gram;
+  const int b0 = kb * 32;
+  const int nb = min(32, C - b0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int i0 = ti * 32 + (wave >> 1) * 16, j0 = tj * 32 + (wave & 1) * 16;
+  const int ci = i0 + col, cj = j0 + col;
+  typedef Mfma<double>::v4 V4;
+  V4 acc[2];
+  for (int v = 0; v < 4; ++v) {
+    acc[0][v] = 0.0;
+    acc[1][v] = 0.0;
+  }
+  for (int l0 = 0; l0 < nb; l0 += 4) {
+    const int l = l0 + grp;
+    z64 x, y;
+    x.re = x.im = y.re = y.im = 0.0;
+    if (l < nb) {
+      if (ci < C) x = G[(size_t)ci * C + b0 + l];
+      if (cj < C) y = G[(size_t)cj * C + b0 + l];
+    }
+    gram_mfma<double>(acc, x, y);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + Mfma<double>::row(lane, v), j = j0 + col;
+    if (i < C && j < C && i <= j) {
+      z64& z = G[(size_t)j * C + i];
+      z.re -= acc[0][v];
+      z.im -= acc[1][v];
+    }
+  }
+}
+
+// X = R^H in FP32 (C x C column-major, lower triangular) into the Jacobi work matrix.
+__global__ void xinit_kernel(const GateDesc* __restrict__ jdescs) {
+  const int g = blockIdx.y;
+  const int C = jdescs[g].C;
+  const z64* __restrict__ G = (const z64*)jdescs[g].gram;
+  z32* __restrict__ X = (z32*)jdescs[g].w;
+  const size_t total = (size_t)C * C;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % C), j = (int)(e / C);
+    z32 z;
+    z.re = z.im = 0.f;
+    if (i >= j) {
+      const z64 r = G[(size_t)i * C + j];  // R[j][i]
+      z.re = (float)r.re;
+      z.im = (float)(-r.im);
+    }
+    X[e] = z;
+  }
+}
+
+// Right vectors of W: Yhat[ps[i], c] = X[i, c] / ||X[:, c]|| for the kept columns
+// c = perm[j], j < k (stored in the G buffer, C x C FP32 column-major).
+__global__ void yhat_kernel(const GateDesc* __restrict__ jdescs, PrecondOut po, LayerOut out) {
+  const int g = blockIdx.y;
+  const int C = jdescs[g].C;
+  const int k = out.k[g];
+  const z32* __restrict__ X = (const z32*)jdescs[g].w;
+  z32* __restrict__ Y = (z32*)jdescs[g].gram;
+  const int* __restrict__ ps = po.ps + (size_t)g * po.cmax;
+  const int* __restrict__ perm = out.perm + (size_t)g * out.cmax;
+  const double* __restrict__ sig = out.sig + (size_t)g * out.cmax;
+  const size_t total = (size_t)C * k;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % C), j = (int)(e / C);
+    const int c = perm[j];
+    const double inv = sig[j] > 0.0 ? 1.0 / sig[j] : 0.0;
+    const z32 x = X[(size_t)c * C + i];
+    z32 z;
+    z.re = (float)(x.re * inv);
+    z.im = (float)(x.im * inv);
+    Y[(size_t)c * C + ps[i]] = z;
+  }
+}
+
+// U S = W Yhat for the kept columns (c = perm[j], j < k): 32 rows x 32 kept columns per
+// workgroup, four waves of 16 x 16, K = C in steps of 4 on FP32 MFMA.  Written into the
+// column c of the U buffer (R x C), unnormalized (the write-back divides by sigma).
+__global__ __launch_bounds__(256) void ugemm_kernel(const GateDesc* __restrict__ descs,
+                                                    LayerOut out) {
+  const int g = blockIdx.y;
+  const GateDesc* d = descs + g;
+  const int R = d->R, C = d->C;
+  const int k = out.k[g];
+  const int tr = (R + 31) >> 5, tk = (k + 31) >> 5;
+  if ((int)blockIdx.x >= tr * tk) return;
+  const int r0 = (blockIdx.x % tr) * 32, j0 = (blockIdx.x / tr) * 32;
+  const z32* __restrict__ W = (const z32*)d->w;
+  const z32* __restrict__ Y = (const z32*)d->gram;
+  z32* __restrict__ U = (z32*)d->left;
+  const int* __restrict__ perm = out.perm + (size_t)g * out.cmax;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int rr = r0 + (wave >> 1) * 16 + col;          // A operand row of this lane
+  const int jb = j0 + (wave & 1) * 16;
+  const int jl = jb + col;                              // B operand column of this lane
+  const int cl = jl < k ? perm[jl] : -1;
+  typedef Mfma<float>::v4 V4;
+  V4 acc[2];
+  for (int v = 0; v < 4; ++v) {
+    acc[0][v] = 0.f;
+    acc[1][v] = 0.f;
+  }
+  for (int k0 = 0; k0 < C; k0 += 4) {
+    const int kk = k0 + grp;
+    z32 a, b;
+    a.re = a.im = b.re = b.im = 0.f;
+    if (kk < C) {
+      if (rr < R) a = W[(size_t)kk * R + rr];
+      if (cl >= 0) b = Y[(size_t)cl * C + kk];
+    }
+    cmfma<float>(acc, a, b);
+  }
+  for (int v = 0; v < 4; ++v) {
+    const int r = r0 + (wave >> 1) * 16 + Mfma<float>::row(lane, v);
+    const int j = jb + col;
+    if (r < R && j < k) {
+      z32 z;
+      z.re = acc[0][v];
+      z.im = acc[1][v];
+      U[(size_t)perm[j] * R + r] = z;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_colsort(const GateDesc* d_desc, int n_gates, const PrecondOut& po,
+                    hipStream_t stream) {
+  hipLaunchKernelGGL(colsort_kernel, dim3(n_gates), dim3(256), 0, stream, d_desc, po);
+}
+
+void launch_gram64(const GateDesc* d_desc, int n_gates, int max_c, const PrecondOut& po,
+                   hipStream_t stream) {
+  const int nt = (max_c + 31) / 32;
+  hipLaunchKernelGGL(gram64_kernel, dim3(nt * (nt + 1) / 2, n_gates), dim3(256), 0, stream,
+                     d_desc, po);
+}
+
+void launch_cholesky(const GateDesc* d_desc, int n_gates, int max_c, const PrecondOut& po,
+                     hipStream_t stream) {
+  const int nt = (max_c + 31) / 32;
+  for (int kb = 0; kb < nt; ++kb) {
+    hipLaunchKernelGGL(potrf_kernel, dim3(n_gates), dim3(256), 0, stream, d_desc, po, kb);
+    const int nrem = nt - kb - 1;
+    if (nrem <= 0) break;
+    hipLaunchKernelGGL(trsm_kernel, dim3(nrem, n_gates), dim3(256), 0, stream, d_desc, kb);
+    hipLaunchKernelGGL(herk_kernel, dim3(nrem * (nrem + 1) / 2, n_gates), dim3(256), 0, stream,
+                       d_desc, kb);
+  }
+}
+
+void launch_xinit(const GateDesc* d_jdesc, int n_gates, int max_c, hipStream_t stream) {
+  const int blocks = std::max(1, std::min(256, (max_c * max_c + 255) / 256));
+  hipLaunchKernelGGL(xinit_kernel, dim3(blocks, n_gates), dim3(256), 0, stream, d_jdesc);
+}
+
+void launch_recover(const GateDesc* d_desc, const GateDesc* d_jdesc, int n_gates, int max_r,
+                    int max_c, const PrecondOut& po, const LayerOut& out, hipStream_t stream) {
+  const int blocks = std::max(1, std::min(256, (max_c * max_c + 255) / 256));
+  hipLaunchKernelGGL(yhat_kernel, dim3(blocks, n_gates), dim3(256), 0, stream, d_jdesc, po, out);
+  const int tiles = ((max_r + 31) / 32) * ((max_c + 31) / 32);
+  hipLaunchKernelGGL(ugemm_kernel, dim3(tiles, n_gates), dim3(256), 0, stream, d_desc, out);
+}
+
+}  // namespace ptebd

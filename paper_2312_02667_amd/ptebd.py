@@ -52,7 +52,7 @@ class KernelStats(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-KERNELS = {"theta": 0, "jacobi": 1, "finalize": 2, "writeback": 3, "sample": 4}
+KERNELS = {"theta": 0, "jacobi": 1, "finalize": 2, "writeback": 3, "sample": 4, "precond": 5}
 
 
 class PtebdError(RuntimeError):
@@ -71,7 +71,7 @@ _SIGS = {
                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "ptebd_mps_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "ptebd_set_svd_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
-                                             ctypes.c_int, ctypes.c_int]),
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "ptebd_apply_layer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, _dp,
                                           ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_int, ctypes.POINTER(LayerStats)]),
@@ -176,11 +176,13 @@ class MPS:
             pass
 
     def set_svd_params(self, max_sweeps: int = 30, tol_factor: float = 4.0,
-                       inner_sweeps: int | None = None, sort_pairs: bool = True):
+                       inner_sweeps: int | None = None, sort_pairs: bool = True,
+                       precondition: bool = True):
         if inner_sweeps is None:
             inner_sweeps = 1 if self.precision == "fp64" else 2
         _check(lib().ptebd_set_svd_params(self._h, int(max_sweeps), float(tol_factor),
-                                          int(inner_sweeps), 1 if sort_pairs else 0))
+                                          int(inner_sweeps), 1 if sort_pairs else 0,
+                                          1 if precondition else 0))
 
     def apply_layer(self, bonds, gates, chi_max: int, cutoff: float = 1e-12, ptsu_steps: int = 0,
                     stabilize: bool = True, state_idx=None, eps_reading: str = "literal") -> dict:

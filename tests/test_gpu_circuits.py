@@ -11,19 +11,22 @@ from tests.gpu_util import lambda_diff, oracle_cutoff, say, to_oracle
 pytestmark = pytest.mark.gpu
 
 
-def test_mixed_path_against_oracle_at_chi_256():
+@pytest.mark.parametrize("precondition", [True, False])
+def test_mixed_path_against_oracle_at_chi_256(precondition):
     """N = 40, depth 14, chi_max = 256, Haar SU(4): bulk bonds saturate (512x512 theta from
-    layer 9); err_F of the FP32 path against the FP64 oracle must stay <= 1e-6."""
+    layer 9); err_F of the FP32 path against the FP64 oracle must stay <= 1e-6, with the
+    preconditioned SVD (the default) and without it."""
     n, depth, chi = 40, 14, 256
     layers = inputs.brickwork_circuit(n, depth, seed=3)
     ref = po.product_state(n)
     m = ptebd.MPS(n, chi, "fp32")
+    m.set_svd_params(precondition=precondition)
     for li, (bonds, gates) in enumerate(layers):
         m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12)
         po.apply_layer(ref, bonds, gates, chi_max=chi, cutoff=oracle_cutoff(1e-12, "fp32"))
         if li + 1 >= 9:
             err = po.fidelity_error(ref, to_oracle(m))
-            say(f"layer {li + 1}: err_F(fp32 GPU vs FP64 oracle) = {err:.3e}")
+            say(f"precondition={precondition} layer {li + 1}: err_F(fp32 GPU vs FP64 oracle) = {err:.3e}")
             assert err <= 1e-6
     assert m.bond_dims() == ref.bond_dims()
     m.close()

