@@ -119,19 +119,31 @@ int ptebd_mps_create(int n_states, const int32_t* n_sites, const int32_t* chi_ca
 /* Free the handle and all its device memory.  NULL is accepted. */
 int ptebd_mps_destroy(ptebd_mps_t h);
 
-/* Set the Jacobi SVD controls of a handle: max_sweeps >= 1 (default 30); the relative
- * off-diagonal tolerance factor tol_factor > 0 (a pair of columns counts as orthogonal when
- * |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit roundoff of the
- * precision; default 4); inner_sweeps in [1, 64], the cyclic sweeps over each 32x32 block
- * pair's Gram matrix (default 2 for FP32, 1 for FP64); sort_pairs 0/1, order each pair's
- * new columns by norm (default 1); precondition 0/1 (FP32 handles only, default 1): sort
- * theta's columns by norm, factor their FP64 Gram matrix G = R^H R (Cholesky) and run the
- * Jacobi on R^H, whose columns start nearly orthogonal, with the left vectors recovered as
- * theta Y / S (about half the sweeps on saturated Haar bonds, and no right-vector
- * accumulation).  FP64 handles ignore it: the Gram matrix would square the condition
- * number and cost the relative accuracy of the FP64 path. */
-int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int inner_sweeps,
-                         int sort_pairs, int precondition);
+/* Controls of the batched one-sided block Jacobi SVD of a handle. */
+typedef struct {
+  int max_sweeps;       /* >= 1, default 30 */
+  double tol_factor;    /* > 0, default 4: a pair of columns counts as orthogonal when
+                           |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit
+                           roundoff of the precision */
+  int inner_sweeps;     /* in [1, 64]: at most this many cyclic sweeps over each 32x32 block
+                           pair's Gram matrix (default 2 for FP32, 1 for FP64) */
+  double inner_repeat;  /* >= 0: a further inner sweep runs only while the previous one rotated
+                           a pair whose cosine |g| / sqrt(a b) exceeded it (0: while it rotated
+                           at all); default 1e-2 for FP32, 0 for FP64 */
+  int sort_pairs;       /* 0/1, default 1: order each pair's new columns by norm */
+  int precondition;     /* 0/1, FP32 handles only, default 1: sort theta's columns by norm,
+                           factor their FP64 Gram matrix G = R^H R (Cholesky) and run the
+                           Jacobi on R^H, whose columns start nearly orthogonal, with the left
+                           vectors recovered as theta Y / S (about half the sweeps on saturated
+                           Haar bonds, and no right-vector accumulation).  FP64 handles ignore
+                           it: the Gram matrix would square the condition number and cost the
+                           relative accuracy of the FP64 path. */
+} ptebd_svd_params;
+
+/* Read (get) or replace (set) the SVD controls of a handle.  set validates every field
+ * (EINVAL, nothing changed).  Both return EINVAL on a NULL pointer. */
+int ptebd_get_svd_params(ptebd_mps_t h, ptebd_svd_params* out);
+int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* params);
 
 /*
  * Apply one circuit layer (one step of Algorithm 1) to states of the batch.

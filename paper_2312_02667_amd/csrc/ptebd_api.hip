@@ -192,6 +192,7 @@ struct ptebd_mps {
   int max_sweeps = 30;
   double tol_factor = 4.0;
   int inner_sweeps = 1;
+  double inner_repeat = 0.0;
   int sort_pairs = 1;
   int precondition = 1;  // FP32 handles only
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -260,7 +261,8 @@ LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
 template <class T>
 int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, const LayerOut& lo,
                int precision, int max_sweeps, double tol_factor, int inner_sweeps,
-               int sort_pairs, int32_t* h_counter, int* n_unconverged, Prof* pf) {
+               double inner_repeat, int sort_pairs, int32_t* h_counter, int* n_unconverged,
+               Prof* pf) {
   ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
   int nb = (max_c + 15) / 16;
   int nbp = nb + (nb & 1);
@@ -271,7 +273,7 @@ int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, con
     for (int round = 0; round < nbp - 1; ++round)
       timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
         ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
-                                      sort_pairs, stream);
+                                      inner_repeat, sort_pairs, stream);
       });
     ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
     PT_HIP(hipGetLastError());
@@ -417,7 +419,8 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
   PT_HIP(hipGetLastError());
   int n_unconv = 0;
   PT_CHECK(run_jacobi<T>(stream, d_jdesc, n, max_c, lo, h->precision, h->max_sweeps,
-                         h->tol_factor, h->inner_sweeps, h->sort_pairs, (int32_t*)h->h_small.p,
+                         h->tol_factor, h->inner_sweeps, h->inner_repeat, h->sort_pairs,
+                         (int32_t*)h->h_small.p,
                          &n_unconv, pf));
   timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_jdesc, n, cutoff, lo, stream); });
   if (pre)
@@ -593,6 +596,7 @@ int ptebd_mps_create(int n_states, const int32_t* n_sites, const int32_t* chi_ca
   // measured at chi = 256 (one saturated layer): FP32 fastest with 2 inner sweeps, FP64
   // with 1 (the FP64 inner sweep costs more than the outer sweeps it saves)
   h->inner_sweeps = precision == PTEBD_FP64 ? 1 : 2;
+  h->inner_repeat = precision == PTEBD_FP64 ? 0.0 : 1e-2;
   h->celem = precision == PTEBD_FP64 ? sizeof(cplx<double>) : sizeof(cplx<float>);
   size_t goff = 0, loff = 0;
   h->st.resize(n_states);
@@ -669,19 +673,33 @@ int ptebd_mps_destroy(ptebd_mps_t h) {
   return PTEBD_OK;
 }
 
-int ptebd_set_svd_params(ptebd_mps_t h, int max_sweeps, double tol_factor, int inner_sweeps,
-                         int sort_pairs, int precondition) {
+int ptebd_get_svd_params(ptebd_mps_t h, ptebd_svd_params* out) {
   PT_CHECK(check_handle(h));
-  if (max_sweeps < 1 || !(tol_factor > 0.0) || !std::isfinite(tol_factor) || inner_sweeps < 1 ||
-      inner_sweeps > 64 || (sort_pairs != 0 && sort_pairs != 1) ||
-      (precondition != 0 && precondition != 1))
+  if (!out) return fail(PTEBD_EINVAL, "params is NULL");
+  out->max_sweeps = h->max_sweeps;
+  out->tol_factor = h->tol_factor;
+  out->inner_sweeps = h->inner_sweeps;
+  out->inner_repeat = h->inner_repeat;
+  out->sort_pairs = h->sort_pairs;
+  out->precondition = h->precondition;
+  return PTEBD_OK;
+}
+
+int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* p) {
+  PT_CHECK(check_handle(h));
+  if (!p) return fail(PTEBD_EINVAL, "params is NULL");
+  if (p->max_sweeps < 1 || !(p->tol_factor > 0.0) || !std::isfinite(p->tol_factor) ||
+      p->inner_sweeps < 1 || p->inner_sweeps > 64 || !(p->inner_repeat >= 0.0) ||
+      !std::isfinite(p->inner_repeat) || (p->sort_pairs != 0 && p->sort_pairs != 1) ||
+      (p->precondition != 0 && p->precondition != 1))
     return fail(PTEBD_EINVAL, "need max_sweeps >= 1, tol_factor > 0, inner_sweeps in [1, 64], "
-                              "sort_pairs and precondition 0/1");
-  h->max_sweeps = max_sweeps;
-  h->tol_factor = tol_factor;
-  h->inner_sweeps = inner_sweeps;
-  h->sort_pairs = sort_pairs;
-  h->precondition = precondition;
+                              "finite inner_repeat >= 0, sort_pairs and precondition 0/1");
+  h->max_sweeps = p->max_sweeps;
+  h->tol_factor = p->tol_factor;
+  h->inner_sweeps = p->inner_sweeps;
+  h->inner_repeat = p->inner_repeat;
+  h->sort_pairs = p->sort_pairs;
+  h->precondition = p->precondition;
   return PTEBD_OK;
 }
 
@@ -1337,7 +1355,7 @@ int svd_batched_t(int precision, int batch, int m, int n, const double* a, doubl
   int32_t counter = 0;
   int n_unconv = 0;
   int st = run_jacobi<T>(stream, (const GateDesc*)desc.p, batch, C, lo, precision, max_sweeps,
-                         tol_factor, 1, 1, &counter, &n_unconv, nullptr);
+                         tol_factor, 1, 0.0, 1, &counter, &n_unconv, nullptr);
   if (st < 0) return cleanup(st);
   ptebd::launch_finalize<T>((const GateDesc*)desc.p, batch, 0.0, lo, stream);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)

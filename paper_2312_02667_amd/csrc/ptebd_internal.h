@@ -99,7 +99,7 @@ void launch_theta(const GateDesc* d_desc, int n_gates, int max_tiles, hipStream_
 template <class T>
 void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
                          const LayerOut& out, double tol_scale, int inner_sweeps,
-                         int sort_pairs, hipStream_t stream);
+                         double inner_repeat, int sort_pairs, hipStream_t stream);
 void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
                         double unit_roundoff, const LayerOut& out, hipStream_t stream);
 template <class T>

@@ -236,7 +236,7 @@ template <class T>
 __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
                                                            int round, int nbp, LayerOut out,
                                                            double tol_scale, int inner_sweeps,
-                                                           int sort_pairs) {
+                                                           double inner_repeat, int sort_pairs) {
   const int g = blockIdx.y;
   if (out.conv[g]) return;
   const GateDesc* d = descs + g;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   __shared__ cplx<T> Q2[32][33];
   __shared__ T P[16][4];  // one round's rotations: c, Re s, Im s
   __shared__ double red[4];
-  __shared__ int flag;
+  __shared__ unsigned int rmax_bits;  // largest |g| / sqrt(a b) rotated in this inner sweep
   __shared__ int pos[32];
   // reduction scratch: wave w < 2 owns region w (3 tiles of 16 x 16), aliasing G / Q
   cplx<T>* part0 = &G[0][0];
@@ -417,18 +417,24 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   const int ra = ia, rb2 = 31 - ia, ca0 = ib, cb2 = 31 - ib;
   auto next_slot = [](int s) { return s >= 2 ? s - 1 : (s == 1 ? 31 : 0); };
   const int nra = next_slot(ra), nrb = next_slot(rb2), nca = next_slot(ca0), ncb = next_slot(cb2);
+  // Another inner sweep follows only while the last one still rotated a pair whose cosine
+  // exceeded inner_repeat: cyclic Jacobi converges quadratically, so after a sweep whose
+  // largest rotated cosine was c the remaining ones are of order c^2.
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     __syncthreads();
-    if (tid == 0) flag = 0;
+    if (tid == 0) rmax_bits = 0u;
     __syncthreads();
     for (int rd = 0; rd < 31; ++rd) {
       if (tid < 16) {
         const int p = tid, q = 31 - tid;
         double c, sr, si;
-        const bool did = jacobi_rotation((double)Gc[p][p].re, (double)Gc[q][q].re,
-                                         (double)Gc[p][q].re, (double)Gc[p][q].im, inner_tol, c,
-                                         sr, si);
-        if (did) flag = 1;
+        const double gpp = (double)Gc[p][p].re, gqq = (double)Gc[q][q].re;
+        const double gr = (double)Gc[p][q].re, gi = (double)Gc[p][q].im;
+        if (jacobi_rotation(gpp, gqq, gr, gi, inner_tol, c, sr, si)) {
+          const double ab = gpp * gqq;
+          const float cosv = ab > 0.0 ? (float)sqrt((gr * gr + gi * gi) / ab) : 3.0e38f;
+          atomicMax(&rmax_bits, __float_as_uint(cosv));
+        }
         P[tid][0] = (T)c;
         P[tid][1] = (T)sr;
         P[tid][2] = (T)si;
@@ -485,8 +491,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
       Qn = tq;
     }
     __syncthreads();
-    const int f = flag;
-    if (f == 0) break;
+    const float rmax = __uint_as_float(rmax_bits);
+    if (!(rmax > (float)inner_repeat) || rmax_bits == 0u) break;
   }
   __syncthreads();
   // Optional ordering of the pair's 32 new columns by norm: the 16 largest go to the
@@ -799,10 +805,11 @@ void launch_jacobi_init(const GateDesc* d_desc, int n_gates, int max_c, const La
 template <class T>
 void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
                          const LayerOut& out, double tol_scale, int inner_sweeps,
+                         double inner_repeat,
                          int sort_pairs, hipStream_t stream) {
   if (n_gates <= 0 || nbp < 2) return;
   hipLaunchKernelGGL(jacobi_round_kernel<T>, dim3(nbp / 2, n_gates), dim3(256), 0, stream,
-                     d_desc, round, nbp, out, tol_scale, inner_sweeps, sort_pairs);
+                     d_desc, round, nbp, out, tol_scale, inner_sweeps, inner_repeat, sort_pairs);
 }
 
 void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
@@ -833,9 +840,9 @@ template void launch_theta<double>(const GateDesc*, int, int, hipStream_t);
 template void launch_jacobi_init<float>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
 template void launch_jacobi_init<double>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
 template void launch_jacobi_round<float>(const GateDesc*, int, int, int, const LayerOut&, double,
-                                         int, int, hipStream_t);
+                                         int, double, int, hipStream_t);
 template void launch_jacobi_round<double>(const GateDesc*, int, int, int, const LayerOut&, double,
-                                          int, int, hipStream_t);
+                                          int, double, int, hipStream_t);
 template void launch_finalize<float>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
 template void launch_finalize<double>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
 template void launch_writeback<float>(const GateDesc*, int, const LayerOut&, hipStream_t);

@@ -47,6 +47,12 @@ class LayerStats(ctypes.Structure):
     ]
 
 
+class SvdParams(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int), ("tol_factor", ctypes.c_double),
+                ("inner_sweeps", ctypes.c_int), ("inner_repeat", ctypes.c_double),
+                ("sort_pairs", ctypes.c_int), ("precondition", ctypes.c_int)]
+
+
 class KernelStats(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double), ("launches", ctypes.c_int64),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -70,8 +76,8 @@ _SIGS = {
     "ptebd_mps_create": (ctypes.c_int, [ctypes.c_int, _i32p, _i32p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "ptebd_mps_destroy": (ctypes.c_int, [ctypes.c_void_p]),
-    "ptebd_set_svd_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
-                                             ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "ptebd_get_svd_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SvdParams)]),
+    "ptebd_set_svd_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SvdParams)]),
     "ptebd_apply_layer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _i32p, _i32p, _dp,
                                           ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_int, ctypes.POINTER(LayerStats)]),
@@ -175,14 +181,21 @@ class MPS:
         except Exception:  # noqa: BLE001
             pass
 
-    def set_svd_params(self, max_sweeps: int = 30, tol_factor: float = 4.0,
-                       inner_sweeps: int | None = None, sort_pairs: bool = True,
-                       precondition: bool = True):
-        if inner_sweeps is None:
-            inner_sweeps = 1 if self.precision == "fp64" else 2
-        _check(lib().ptebd_set_svd_params(self._h, int(max_sweeps), float(tol_factor),
-                                          int(inner_sweeps), 1 if sort_pairs else 0,
-                                          1 if precondition else 0))
+    def svd_params(self) -> dict:
+        p = SvdParams()
+        _check(lib().ptebd_get_svd_params(self._h, ctypes.byref(p)))
+        return {name: getattr(p, name) for name, _ in SvdParams._fields_}
+
+    def set_svd_params(self, **changes):
+        """Change some SVD controls (max_sweeps, tol_factor, inner_sweeps, inner_repeat,
+        sort_pairs, precondition); the others keep their current values."""
+        p = SvdParams()
+        _check(lib().ptebd_get_svd_params(self._h, ctypes.byref(p)))
+        for name, value in changes.items():
+            if name not in dict(SvdParams._fields_):
+                raise TypeError(f"unknown SVD control {name!r}")
+            setattr(p, name, type(getattr(p, name))(value))
+        _check(lib().ptebd_set_svd_params(self._h, ctypes.byref(p)))
 
     def apply_layer(self, bonds, gates, chi_max: int, cutoff: float = 1e-12, ptsu_steps: int = 0,
                     stabilize: bool = True, state_idx=None, eps_reading: str = "literal") -> dict:
