@@ -151,7 +151,8 @@ int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* params);
  *   state_idx    [n_gates] state of each gate, or NULL when the handle holds one state;
  *   bonds        [n_gates] left site q of each gate, 0 <= q <= N-2;
  *   gates        [n_gates * 32] doubles: 16 complex128 per gate (see conventions);
- *   chi_max      >= 1 and <= the state's chi_cap: bond-dimension bound chi;
+ *   chi_max      bond-dimension bound chi, in [1, the state's chi_cap]; or 0: every gate
+ *                is bounded by its own state's chi_cap (states of different caps, one launch);
  *   cutoff       >= 0: singular values sigma <= cutoff * sigma_1 are always dropped
  *                (their weight counts in eps_i); on the FP32 path the cutoff is at least
  *                PTEBD_FP32_CUTOFF_FLOOR;

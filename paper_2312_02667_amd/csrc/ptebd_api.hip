@@ -97,11 +97,13 @@ struct StateInfo {
   double prod_fid = 1.0;
 };
 
-// One bond update: gate (host pointer to 32 doubles) at q of state s, or the identity.
+// One bond update: gate (host pointer to 32 doubles) at q of state s, or the identity; chi
+// is its truncation bound (0: a tSU step, bounded by chi_{q+1} only).
 struct Item {
   int s;
   int q;
   const double* gate;
+  int chi;
 };
 
 struct UpdateResult {
@@ -290,7 +292,7 @@ int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, con
 
 // One batch of independent bond updates (all gates of a layer, or one PtSU half-step).
 template <class T>
-int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, double cutoff,
+int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
                 int stabilize, int eps_mode, UpdateResult* res) {
   const int n = (int)items.size();
   res->k.assign(n, 0);
@@ -323,9 +325,9 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
     d.R = std::max(m, nn);
     d.C = std::min(m, nn);
     d.has_gate = items[i].gate != nullptr ? 1 : 0;
-    // tSU (chi_max <= 0): theta = A B has rank <= chi_{q+1}, so the kept dimension is
+    // tSU (item chi 0): theta = A B has rank <= chi_{q+1}, so the kept dimension is
     // bounded by it; singular values beyond it are rounding noise of the precision.
-    d.chi_max = chi_max > 0 ? chi_max : d.cm;
+    d.chi_max = items[i].chi > 0 ? items[i].chi : d.cm;
     d.stabilize = stabilize;
     d.eps_mode = eps_mode;
     woff[i] = total;
@@ -476,13 +478,13 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, int chi_max, doubl
   return PTEBD_OK;
 }
 
-int run_updates_dispatch(ptebd_mps* h, const std::vector<Item>& items, int chi_max,
-                         double cutoff, int stabilize, int eps_mode, UpdateResult* res) {
+int run_updates_dispatch(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
+                         int stabilize, int eps_mode, UpdateResult* res) {
   if (h->precision == PTEBD_FP64)
-    return run_updates<double>(h, items, chi_max, cutoff, stabilize, eps_mode, res);
+    return run_updates<double>(h, items, cutoff, stabilize, eps_mode, res);
   // FP32 arithmetic leaves rounding residues of up to 2^-20 sigma_1 where an exactly
   // rank-deficient theta has zero singular values; the floor keeps them out of Lambda.
-  return run_updates<float>(h, items, chi_max, std::max(cutoff, PTEBD_FP32_CUTOFF_FLOOR),
+  return run_updates<float>(h, items, std::max(cutoff, PTEBD_FP32_CUTOFF_FLOOR),
                             stabilize, eps_mode, res);
 }
 
@@ -509,9 +511,9 @@ int run_ptsu(ptebd_mps* h, const std::vector<int>& states, int steps, double cut
     for (int parity = 0; parity < 2; ++parity) {
       std::vector<Item> items;
       for (int s : states)
-        for (int q = parity; q + 1 < h->st[s].n; q += 2) items.push_back({s, q, nullptr});
+        for (int q = parity; q + 1 < h->st[s].n; q += 2) items.push_back({s, q, nullptr, 0});
       UpdateResult res;
-      PT_CHECK(run_updates_dispatch(h, items, 0, cutoff, 0, 0, &res));
+      PT_CHECK(run_updates_dispatch(h, items, cutoff, 0, 0, &res));
       *max_sweeps = std::max(*max_sweeps, res.max_sweeps);
       *n_unconv += res.n_unconverged;
     }
@@ -717,7 +719,7 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
     return fail(PTEBD_EINVAL, "unknown flags");
   if ((flags & PTEBD_FLAG_RELATIVE_EPS) && (flags & PTEBD_FLAG_COMPLEMENT_EPS))
     return fail(PTEBD_EINVAL, "RELATIVE_EPS and COMPLEMENT_EPS exclude each other");
-  if (chi_max < 1) return fail(PTEBD_EINVAL, "chi_max must be >= 1");
+  if (chi_max < 0) return fail(PTEBD_EINVAL, "chi_max must be >= 0");
   std::vector<std::vector<char>> used(h->st.size());
   std::vector<Item> items(n_gates);
   for (int i = 0; i < n_gates; ++i) {
@@ -725,6 +727,7 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
     if (s < 0 || s >= (int)h->st.size()) return fail(PTEBD_EINVAL, "state index out of range");
     const StateInfo& si = h->st[s];
     if (chi_max > si.cap) return fail(PTEBD_EINVAL, "chi_max exceeds the state's chi_cap");
+    const int chi = chi_max > 0 ? chi_max : si.cap;
     const int q = bonds[i];
     if (q < 0 || q + 1 >= si.n) return fail(PTEBD_EINVAL, "bond q out of range");
     if (used[s].empty()) used[s].assign(si.n, 0);
@@ -733,12 +736,12 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
     used[s][q] = used[s][q + 1] = 1;
     if (!finite_all(gates + 32 * (size_t)i, 32)) return fail(PTEBD_EINVAL, "non-finite gate entry");
     // the new bond must fit the slot: min(2 chi_q, 2 chi_{q+2}) is capped by chi_max
-    items[i] = {s, q, gates + 32 * (size_t)i};
+    items[i] = {s, q, gates + 32 * (size_t)i, chi};
   }
   PT_CHECK(set_device(h));
   PT_HIP(hipEventRecord(h->ev0, h->stream));
   UpdateResult res;
-  PT_CHECK(run_updates_dispatch(h, items, chi_max, cutoff,
+  PT_CHECK(run_updates_dispatch(h, items, cutoff,
                                 (flags & PTEBD_FLAG_NO_STABILIZE) ? 0 : 1,
                                 (flags & PTEBD_FLAG_RELATIVE_EPS)     ? 1
                                 : (flags & PTEBD_FLAG_COMPLEMENT_EPS) ? 2
@@ -747,7 +750,7 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
   std::vector<int> trig_states;
   std::vector<char> trig(h->st.size(), 0);
   for (int i = 0; i < n_gates; ++i)
-    if (res.r[i] > chi_max) trig[items[i].s] = 1;
+    if (res.r[i] > items[i].chi) trig[items[i].s] = 1;
   for (size_t s = 0; s < trig.size(); ++s)
     if (trig[s]) trig_states.push_back((int)s);
   for (int i = 0; i < n_gates; ++i) {
@@ -809,9 +812,9 @@ int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out) {
   for (int pass = 0; pass < 2; ++pass)
     for (int t = 0; t + 1 < n; ++t) {
       const int q = pass == 0 ? t : n - 2 - t;
-      std::vector<Item> items{Item{s, q, nullptr}};
+      std::vector<Item> items{Item{s, q, nullptr, 0}};
       UpdateResult res;
-      PT_CHECK(run_updates_dispatch(h, items, 0, cutoff, 0, 0, &res));
+      PT_CHECK(run_updates_dispatch(h, items, cutoff, 0, 0, &res));
       n_unconv += res.n_unconverged;
     }
   const StateInfo& si = h->st[s];

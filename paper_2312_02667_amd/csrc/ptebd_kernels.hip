@@ -109,9 +109,9 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
         cplx<T> val = czero<T>();
         if (ga < cl && gk < cm) {
           const cplx<T> g = gq[s * plane_a + (size_t)gk * cl + ga];
-          const double sc = lam_l[ga] * lam_m[gk];
-          val.re = (T)((double)g.re * sc);
-          val.im = (T)((double)g.im * sc);
+          const T sc = (T)(lam_l[ga] * lam_m[gk]);
+          val.re = g.re * sc;
+          val.im = g.im * sc;
         }
         As[s][k][a] = val;
       }
@@ -121,9 +121,9 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
         cplx<T> val = czero<T>();
         if (gc < cr && gk < cm) {
           const cplx<T> g = gq1[s * plane_b + (size_t)gc * cm + gk];
-          const double sc = lam_r[gc];
-          val.re = (T)((double)g.re * sc);
-          val.im = (T)((double)g.im * sc);
+          const T sc = (T)lam_r[gc];
+          val.re = g.re * sc;
+          val.im = g.im * sc;
         }
         Bs[s][k][c] = val;
       }
@@ -242,8 +242,14 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   const GateDesc* d = descs + g;
   const int R = d->R, C = d->C;
   const int nb = (C + 15) >> 4;
-  const int I = rr_player(blockIdx.x, round, nbp);
-  const int J = rr_player(nbp - 1 - blockIdx.x, round, nbp);
+  // Each gate follows its own tournament of nbg players (its block count, made even): the
+  // launch covers the batch's largest, and a gate sits out the rounds and pairs beyond its
+  // own, so its sequence of rotations does not depend on what it is batched with.
+  const int nbg = max(2, nb + (nb & 1));
+  (void)nbp;
+  if (round >= nbg - 1 || (int)blockIdx.x >= nbg / 2) return;
+  const int I = rr_player(blockIdx.x, round, nbg);
+  const int J = rr_player(nbg - 1 - blockIdx.x, round, nbg);
   const bool dummy_i = I >= nb, dummy_j = J >= nb;
   if (dummy_i && dummy_j) return;
   // A pair with the padding player is skipped, except when the matrix has a single block:

@@ -1,0 +1,142 @@
+"""Parity on the two remaining workload shapes: a 2D circuit on an 8 x 8 lattice compiled to
+the 64-site column path (SWAP routing) at chi_max = 512, and a batched mix of independent
+circuits of different lengths and bond-dimension caps in one launch per layer.  Both run in
+full on the GPU; the oracle recomputes sampled bond updates from the GPU's own state before
+the layer (one 1024 x 1024 SVD at chi = 512 takes the oracle seconds)."""
+
+import numpy as np
+import pytest
+
+from oracle import ptebd_oracle as po
+from paper_2312_02667_amd import circuits, inputs, ptebd
+from tests.gpu_util import oracle_cutoff, say
+
+pytestmark = pytest.mark.gpu
+
+# FP32 path against FP64 on the same input: sigma abs error / sigma_1 and relative Frobenius
+# error of the gauge-invariant two-site tensor.  eps is a sum of sigma^2 (discarded ones, or
+# 1 - the kept ones), so |d eps| <= 2 sum_j sigma_j |d sigma_j| <= 2 lam sigma_1 sum_j sigma_j.
+TOL32 = dict(lam=2e-5, th=5e-5)
+
+
+def _two_site(gq, lam_l, lam_m, gq1, lam_r):
+    a = lam_l[:, None, None] * gq * lam_m[None, None, :]
+    b = gq1 * lam_r[None, None, :]
+    return np.einsum("asm,mtc->astc", a, b)
+
+
+def _check_bond(m, s, q, gate, before, st_k, st_eps, chi, label, reading="literal"):
+    """before: (Gamma[q], Gamma[q+1], Lambda[q..q+2]) exported before the layer."""
+    g0, g1, l0, l1, l2 = before
+    local = po.VidalMPS([g0, g1], [l0, l1, l2])
+    ref = po.bond_update(local, 0, gate, chi, oracle_cutoff(1e-12, "fp32"), stabilize=True,
+                         eps_reading=reading)
+    s1 = ref["sigma"][0]
+    lam_gpu = m.get_lambda(q + 1, s)
+    say(f"  {label} q={q}: theta {2 * len(l0)}x{2 * len(l2)}, k={ref['k']} (gpu {st_k})")
+    assert st_k == ref["k"]
+    assert np.max(np.abs(lam_gpu - local.lam[1])) <= TOL32["lam"] * s1
+    assert abs(st_eps - ref["eps"]) <= 2 * TOL32["lam"] * s1 * float(np.sum(ref["sigma"]))
+    th_ref = _two_site(local.gam[0], l0, local.lam[1], local.gam[1], l2)
+    th_gpu = _two_site(m.export_site(q, s), l0, lam_gpu, m.export_site(q + 1, s), l2)
+    err = np.linalg.norm(th_gpu - th_ref) / np.linalg.norm(th_ref)
+    say(f"    two-site rel. error {err:.2e}")
+    assert err <= TOL32["th"]
+
+
+def _export_bond(m, s, q):
+    return (m.export_site(q, s), m.export_site(q + 1, s), m.get_lambda(q, s),
+            m.get_lambda(q + 1, s), m.get_lambda(q + 2, s))
+
+
+def test_2d_lattice_chi512_sampled_parity():
+    """8 x 8 lattice, Haar SU(4) gates on the couplings of layers A, B, C, D (physical depth
+    12), compiled to the column path (C and D routed by SWAP layers: 75 compiled layers),
+    chi_max = 512, mixed precision, the complement reading of eps (under the literal one the
+    norm grows with every saturated layer of this circuit until a discarded weight reaches 1).
+    At each of the last three compiled layers, the largest bond update is recomputed by the
+    oracle from the GPU's state before the layer."""
+    lx = ly = 8
+    rng = np.random.default_rng(404)
+    physical = []
+    for layer in range(12):
+        kind = layer % 4
+        physical.append((kind, {}, [(a, b, inputs.haar_unitary(rng))
+                                    for a, b in circuits.lattice_couplings(lx, ly, kind)]))
+    layers = circuits.compile_2d(lx, ly, physical)
+    n, chi = lx * ly, 512
+    m = ptebd.MPS(n, chi, "fp32")
+    checked = 0
+    for li, (bonds, gates) in enumerate(layers):
+        sample = li >= len(layers) - 3
+        dims = m.bond_dims()
+        if sample:
+            sizes = [dims[q] * dims[q + 2] for q in bonds]
+            i = int(np.argmax(sizes))
+            before = _export_bond(m, 0, int(bonds[i]))
+        st = m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12, eps_reading="complement")
+        assert st["n_unconverged"] == 0
+        if li % 10 == 0 or sample:
+            say(f"2D 8x8 compiled layer {li + 1}/{len(layers)}: max bond {max(m.bond_dims())}, "
+                f"{st['device_ms']:.1f} ms")
+        if sample:
+            _check_bond(m, 0, int(bonds[i]), gates[i], before, int(st["k"][i]),
+                        float(st["eps"][i]), chi, f"layer {li + 1}", reading="complement")
+            checked += 1
+    assert checked == 3
+    assert max(m.bond_dims()) == chi      # the largest bonds reached the cap
+    m.close()
+
+
+def test_batched_mix_of_circuits_sampled_parity():
+    """64 independent 1D Haar circuits, N uniform in [50, 400], chi_max drawn from
+    {64, 128, 256}, depth 16, mixed precision, all in one handle: one apply_layer per layer
+    with chi_max = 0 (each gate truncated to its own state's cap).  Four circuits are also
+    run alone and must agree bit for bit; in the last layer two bonds of four circuits are
+    recomputed by the oracle."""
+    rng = np.random.default_rng(505)
+    n_circ, depth = 64, 16
+    ns = rng.integers(50, 401, n_circ)
+    caps = rng.choice([64, 128, 256], n_circ)
+    circs = [inputs.brickwork_circuit(int(n), depth, seed=600, circuit_id=c) for c, n in enumerate(ns)]
+    say(f"batched mix: {n_circ} circuits, {int(ns.sum())} sites, caps {np.bincount(caps)[[64, 128, 256]]}")
+    batched = ptebd.MPS([int(x) for x in ns], [int(x) for x in caps], "fp32")
+    alone_ids = [int(np.argmax(caps == 256)), int(np.argmax(caps == 64)), 5, 17]
+    alone = {c: ptebd.MPS(int(ns[c]), int(caps[c]), "fp32") for c in alone_ids}
+    check_ids = alone_ids
+    for layer in range(depth):
+        sidx, bonds, gates = [], [], []
+        for c, circ in enumerate(circs):
+            b, g = circ[layer]
+            sidx.append(np.full(len(b), c, np.int32))
+            bonds.append(b)
+            gates.append(g)
+        sidx, bonds, gates = np.concatenate(sidx), np.concatenate(bonds), np.concatenate(gates)
+        last = layer == depth - 1
+        befores = {}
+        if last:
+            for c in check_ids:
+                sel = np.where(sidx == c)[0]
+                for i in (sel[len(sel) // 2], sel[-1]):
+                    befores[int(i)] = _export_bond(batched, c, int(bonds[i]))
+        st = batched.apply_layer(bonds, gates, chi_max=0, cutoff=1e-12, state_idx=sidx)
+        assert st["n_unconverged"] == 0
+        say(f"batched mix layer {layer + 1}: {len(bonds)} gates, {st['device_ms']:.1f} ms, "
+            f"max sweeps {st['max_sweeps']}")
+        for c in alone_ids:
+            b, g = circs[c][layer]
+            alone[c].apply_layer(b, g, chi_max=int(caps[c]), cutoff=1e-12)
+        if last:
+            for i, before in befores.items():
+                c = int(sidx[i])
+                _check_bond(batched, c, int(bonds[i]), gates[i], before, int(st["k"][i]),
+                            float(st["eps"][i]), int(caps[c]), f"circuit {c} (N={ns[c]}, cap {caps[c]})")
+    for c in alone_ids:
+        assert batched.bond_dims(c) == alone[c].bond_dims()
+        assert max(batched.bond_dims(c)) <= caps[c]
+        gb, lb = batched.export(c)
+        ga, la = alone[c].export()
+        assert all(np.array_equal(x, y) for x, y in zip(lb, la))
+        assert all(np.array_equal(x, y) for x, y in zip(gb, ga))
+        alone[c].close()
+    batched.close()
