@@ -213,8 +213,15 @@ namespace {
 
 // Layout of the per-gate output block inside outbuf.
 struct OutLayout {
-  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, work, ps, gmax, total;
+  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, ps, gmax, work, total;
+  int nslot;
 };
+
+// Column-block pairs per round of the block Jacobi for matrices of up to cmax columns.
+int pair_slots(int cmax) {
+  const int nb = (cmax + 15) / 16;
+  return std::max(2, nb + (nb & 1)) / 2;
+}
 
 OutLayout out_layout(int n, int cmax) {
   OutLayout L;
@@ -234,9 +241,10 @@ OutLayout out_layout(int n, int cmax) {
   L.conv = take(sizeof(int32_t) * n);
   L.offbits = take(sizeof(uint32_t) * n);
   L.counters = take(sizeof(int32_t) * 4);
-  L.work = take(sizeof(unsigned long long) * 4);
   L.ps = take(sizeof(int32_t) * (size_t)n * cmax);
   L.gmax = take(sizeof(double) * n);
+  L.nslot = pair_slots(cmax);
+  L.work = take(sizeof(uint32_t) * 2 * (size_t)n * L.nslot);
   L.total = off;
   return L;
 }
@@ -254,7 +262,8 @@ LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
   o.conv = (int32_t*)(b + L.conv);
   o.offbits = (uint32_t*)(b + L.offbits);
   o.counters = (int32_t*)(b + L.counters);
-  o.work = (unsigned long long*)(b + L.work);
+  o.work = (uint32_t*)(b + L.work);
+  o.nslot = L.nslot;
   o.cmax = cmax;
   return o;
 }
@@ -455,9 +464,25 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   if (pf->on) {
     pf->harvest();
     const double ce = (double)sizeof(cplx<T>);
-    const unsigned long long* hw = (const unsigned long long*)(ho + L.work);
-    pf->st[PTEBD_KERNEL_JACOBI].flops += 6144.0 * (double)hw[0] + 8192.0 * (double)hw[1];
-    pf->st[PTEBD_KERNEL_JACOBI].bytes += ce * (32.0 * (double)hw[0] + 64.0 * (double)hw[1]);
+    // executed Jacobi pairs per gate: Gram pairs cost 6144 R flops and 32 R complex reads,
+    // rotated pairs 8192 (R + C) flops and 64 (R + C) complex reads and writes (R + 0 when
+    // the right vectors are not accumulated)
+    const size_t wn = sizeof(uint32_t) * 2 * (size_t)n * L.nslot;
+    PT_HIP(hipMemcpyAsync((char*)h->h_out.p + L.work, (char*)h->outbuf.p + L.work, wn,
+                          hipMemcpyDeviceToHost, stream));
+    PT_HIP(hipStreamSynchronize(stream));
+    const uint32_t* hw = (const uint32_t*)(ho + L.work);
+    const GateDesc* hj = (const GateDesc*)h->h_desc.p + (pre ? n : 0);
+    for (int i = 0; i < n; ++i) {
+      double pairs = 0.0, rotated = 0.0;
+      for (int x = 0; x < L.nslot; ++x) {
+        pairs += hw[2 * ((size_t)i * L.nslot + x)];
+        rotated += hw[2 * ((size_t)i * L.nslot + x) + 1];
+      }
+      const double rj = hj[i].R, rot_rows = rj + (hj[i].v != nullptr ? (double)hj[i].C : 0.0);
+      pf->st[PTEBD_KERNEL_JACOBI].flops += 6144.0 * rj * pairs + 8192.0 * rot_rows * rotated;
+      pf->st[PTEBD_KERNEL_JACOBI].bytes += ce * (32.0 * rj * pairs + 64.0 * rot_rows * rotated);
+    }
     for (int i = 0; i < n; ++i) {
       const GateDesc& d = descs[i];
       const double cl = d.cl, cm = d.cm, cr = d.cr, kk = hk[i];

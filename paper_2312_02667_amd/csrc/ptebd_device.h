@@ -58,21 +58,89 @@ __device__ inline cplx<T> czero() {
   return z;
 }
 
+// Device memory reached through a pointer read from a descriptor.  Such a pointer is
+// generic to the compiler, and generic (flat) accesses count against the LDS counter as
+// well as the vector-memory one: every wait for an LDS result would then also wait for the
+// global loads in flight, which defeats prefetching.  Casting it to the global address
+// space gives global loads and stores (and the scalar-base + 32-bit offset form).
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+// Native vector types for 16-byte global accesses (plain loads and stores, no class copy
+// through an address-space-qualified reference).
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ inline gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+
+// One complex entry read through a global pointer (by value, for use in expressions that
+// mix it with local values).
+template <class T>
+__device__ inline cplx<T> gload(gptr<const cplx<T>> p) {
+  cplx<T> z;
+  z.re = p->re;
+  z.im = p->im;
+  return z;
+}
+
+template <class T>
+__device__ inline void gstore(gptr<cplx<T>> p, cplx<T> z) {
+  p->re = z.re;
+  p->im = z.im;
+}
+
+// Entry idx of a global complex array addressed by a 32-bit element index (every array
+// indexed this way holds well under 2^28 entries), which lets the compiler use the scalar
+// base + 32-bit vector offset address form instead of a 64-bit address per lane.
+template <class T>
+__device__ inline gptr<const cplx<T>> gat(gptr<const cplx<T>> base, uint32_t idx) {
+  return (gptr<const cplx<T>>)((gptr<const char>)base + idx * (uint32_t)sizeof(cplx<T>));
+}
+template <class T>
+__device__ inline gptr<cplx<T>> gat(gptr<cplx<T>> base, uint32_t idx) {
+  return (gptr<cplx<T>>)((gptr<char>)base + idx * (uint32_t)sizeof(cplx<T>));
+}
+
+// Entries idx and idx + 1 (idx even for FP32: one 16-byte load).
+template <class T>
+__device__ inline void gload_pair(gptr<const cplx<T>> base, uint32_t idx, cplx<T>& a,
+                                  cplx<T>& b) {
+  if constexpr (sizeof(T) == 4) {
+    const vf4 u = *reinterpret_cast<gptr<const vf4>>(gat<T>(base, idx));
+    a.re = u.x; a.im = u.y; b.re = u.z; b.im = u.w;
+  } else {
+    a = gload<T>(gat<T>(base, idx));
+    b = gload<T>(gat<T>(base, idx + 1));
+  }
+}
+
+// z when ok, else 0 (a select, no branch).
+template <class T>
+__device__ inline cplx<T> cmask(cplx<T> z, bool ok) {
+  cplx<T> o;
+  o.re = ok ? z.re : T(0);
+  o.im = ok ? z.im : T(0);
+  return o;
+}
+
 // Four consecutive complex entries from 16-byte aligned memory (zeros when !ok).
 template <class T>
-__device__ inline void load4(bool ok, const cplx<T>* __restrict__ p, cplx<T> (&o)[4]) {
+__device__ inline void load4(bool ok, gptr<const cplx<T>> p, cplx<T> (&o)[4]) {
   if (!ok) {
     for (int t = 0; t < 4; ++t) o[t] = czero<T>();
     return;
   }
   if constexpr (sizeof(T) == 4) {
-    const float4 u = *reinterpret_cast<const float4*>(p);
-    const float4 w = *reinterpret_cast<const float4*>(p + 2);
+    const vf4 u = *reinterpret_cast<gptr<const vf4>>(p);
+    const vf4 w = *reinterpret_cast<gptr<const vf4>>(p + 2);
     o[0].re = u.x; o[0].im = u.y; o[1].re = u.z; o[1].im = u.w;
     o[2].re = w.x; o[2].im = w.y; o[3].re = w.z; o[3].im = w.w;
   } else {
     for (int t = 0; t < 4; ++t) {
-      const double2 u = *reinterpret_cast<const double2*>(p + t);
+      const vd2 u = *reinterpret_cast<gptr<const vd2>>(p + t);
       o[t].re = u.x;
       o[t].im = u.y;
     }

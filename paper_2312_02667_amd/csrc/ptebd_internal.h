@@ -66,9 +66,13 @@ struct LayerOut {
   uint32_t* offbits; // max relative off-diagonal of the sweep (float bits)
   int32_t* counters; // [0..1] unconverged counts (double-buffered by sweep parity),
                      // [2] error flags: bit0 annihilated, bit1 non-finite
-  unsigned long long* work;  // executed Jacobi work: [0] sum R over Gram pairs,
-                             // [1] sum (R + C) over rotated pairs, [2] Gram pairs,
-                             // [3] rotated pairs
+  uint32_t* work;    // executed Jacobi pairs per (gate, pair slot): work[2 (g nslot + x)] counts
+                     // the pairs whose Gram matrix was formed, work[2 (g nslot + x) + 1] the
+                     // rotated ones.  One workgroup owns a slot in a launch, so these counts
+                     // never contend (a handful of shared counters for every workgroup of a
+                     // launch serialize in one L2 channel and cost a large share of the
+                     // Gram phase).
+  int32_t nslot;     // pair slots per gate: half the even block count of cmax
   int32_t cmax;
 };
 

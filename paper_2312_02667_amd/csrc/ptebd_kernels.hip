@@ -5,6 +5,8 @@
 //   finalize_kernel  -- singular values, sort, truncation and discarded weight (Sec. III.B,
 //                       Theorem 1), norm stabilization nu (Sec. III.C.2, Eq. (lren))
 //   writeback_kernel -- Vidal regauge with Lambda^{-1} (Sec. II.C) into the state arena
+#include <type_traits>
+
 #include "ptebd_device.h"
 #include "ptebd_internal.h"
 
@@ -92,11 +94,11 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
     for (int j = 0; j < 2; ++j)
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
 
-  const cplx<T>* __restrict__ gq = (const cplx<T>*)d->gq;
-  const cplx<T>* __restrict__ gq1 = (const cplx<T>*)d->gq1;
-  const double* __restrict__ lam_l = d->lam_l;
-  const double* __restrict__ lam_m = d->lam_m;
-  const double* __restrict__ lam_r = d->lam_r;
+  const gptr<const cplx<T>> __restrict__ gq = as_global((const cplx<T>*)d->gq);
+  const gptr<const cplx<T>> __restrict__ gq1 = as_global((const cplx<T>*)d->gq1);
+  const gptr<const double> __restrict__ lam_l = as_global(d->lam_l);
+  const gptr<const double> __restrict__ lam_m = as_global((const double*)d->lam_m);
+  const gptr<const double> __restrict__ lam_r = as_global(d->lam_r);
   const size_t plane_a = (size_t)cl * cm, plane_b = (size_t)cm * cr;
 
   for (int k0 = 0; k0 < cm; k0 += 16) {
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
         const int ga = a0 + a, gk = k0 + k;
         cplx<T> val = czero<T>();
         if (ga < cl && gk < cm) {
-          const cplx<T> g = gq[s * plane_a + (size_t)gk * cl + ga];
+          const cplx<T> g = gload<T>(gq + (s * plane_a + (size_t)gk * cl + ga));
           const T sc = (T)(lam_l[ga] * lam_m[gk]);
           val.re = g.re * sc;
           val.im = g.im * sc;
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
         const int gc = c0 + c, gk = k0 + k;
         cplx<T> val = czero<T>();
         if (gc < cr && gk < cm) {
-          const cplx<T> g = gq1[s * plane_b + (size_t)gc * cm + gk];
+          const cplx<T> g = gload<T>(gq1 + (s * plane_b + (size_t)gc * cm + gk));
           const T sc = (T)lam_r[gc];
           val.re = g.re * sc;
           val.im = g.im * sc;
@@ -148,11 +150,11 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
   T ur[16], ui[16];
   if (has_gate) {
     for (int i = 0; i < 16; ++i) {
-      ur[i] = (T)d->gate[2 * i];
-      ui[i] = (T)d->gate[2 * i + 1];
+      ur[i] = (T)as_global(d->gate)[2 * i];
+      ui[i] = (T)as_global(d->gate)[2 * i + 1];
     }
   }
-  cplx<T>* __restrict__ w = (cplx<T>*)d->w;
+  const gptr<cplx<T>> __restrict__ w = as_global((cplx<T>*)d->w);
   for (int v = 0; v < 4; ++v) {
     const int a = a0 + wa * 16 + Mfma<T>::row(lane, v);
     const int c = c0 + wc * 16 + (lane & 15);
@@ -182,10 +184,10 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
         o.re = tr;
         if (!transposed) {
           o.im = ti;
-          w[(size_t)col * R + row] = o;
+          gstore<T>(w + ((size_t)col * R + row), o);
         } else {
           o.im = -ti;
-          w[(size_t)row * R + col] = o;
+          gstore<T>(w + ((size_t)row * R + col), o);
         }
       }
     }
@@ -199,24 +201,27 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
   const int g = blockIdx.y;
   const GateDesc* d = descs + g;
   const int C = d->C;
-  cplx<T>* v = (cplx<T>*)d->v;
+  const gptr<cplx<T>> v = as_global((cplx<T>*)d->v);
   const size_t total = v != nullptr ? (size_t)C * C : 0;  // no V: right vectors not kept
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const size_t col = e / C, row = e % C;
     cplx<T> z = czero<T>();
     if (row == col) z.re = T(1);
-    v[e] = z;
+    gstore<T>(v + e, z);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    out.conv[g] = 0;
-    out.sweeps[g] = 0;
-    out.offbits[g] = 0u;
-    if (g == 0) {
-      out.counters[0] = 0;
-      out.counters[1] = 0;
-      out.counters[2] = 0;
-      for (int i = 0; i < 4; ++i) out.work[i] = 0ull;
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < 2 * out.nslot; i += blockDim.x)
+      out.work[(size_t)g * 2 * out.nslot + i] = 0u;
+    if (threadIdx.x == 0) {
+      out.conv[g] = 0;
+      out.sweeps[g] = 0;
+      out.offbits[g] = 0u;
+      if (g == 0) {
+        out.counters[0] = 0;
+        out.counters[1] = 0;
+        out.counters[2] = 0;
+      }
     }
   }
 }
@@ -229,11 +234,13 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
 // on MFMA.  Pairs of one round are disjoint, so no two workgroups of a gate touch the same
 // column.
 //
-// LDS: G and Q with their next-round copies (4 x 32 x 33 complex T); the cross-wave
-// reduction of the Gram tiles and the permuted copy of Q used by the column update alias
-// them.
+// LDS: G and Q (2 x 32 x 33 complex T), both rotated in place; the cross-wave reduction of
+// the Gram tiles and the permuted copy of Q used by the column update alias them.
+//
+// Occupancy: the kernel is bound by the latency of its phases, so it is built for five waves
+// per SIMD in FP32 (at most 96 registers, no spills) and three in FP64 (at most 168).
 template <class T>
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
                                                            int round, int nbp, LayerOut out,
                                                            double tol_scale, int inner_sweeps,
                                                            double inner_repeat, int sort_pairs) {
@@ -257,13 +264,11 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   if ((dummy_i || dummy_j) && nb > 1) return;
   const int cI = dummy_i ? 0 : I * 16, cJ = dummy_j ? 0 : J * 16;
   const int nI = dummy_i ? 0 : min(16, C - cI), nJ = dummy_j ? 0 : min(16, C - cJ);
-  cplx<T>* __restrict__ W = (cplx<T>*)d->w;
-  cplx<T>* __restrict__ V = (cplx<T>*)d->v;
+  const gptr<cplx<T>> __restrict__ W = as_global((cplx<T>*)d->w);
+  const gptr<cplx<T>> __restrict__ V = as_global((cplx<T>*)d->v);
 
   __shared__ cplx<T> G[32][33];
-  __shared__ cplx<T> G2[32][33];
   __shared__ cplx<T> Q[32][33];
-  __shared__ cplx<T> Q2[32][33];
   __shared__ T P[16][4];  // one round's rotations: c, Re s, Im s
   __shared__ double red[4];
   __shared__ unsigned int rmax_bits;  // largest |g| / sqrt(a b) rotated in this inner sweep
@@ -272,51 +277,78 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   cplx<T>* part0 = &G[0][0];
   cplx<T>* part1 = &Q[0][0];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar loop bounds
   const int col = lane & 15, grp = lane >> 4;
   typedef typename Mfma<T>::v4 V4;
 
-  // ---- Gram matrix: rows split over the four waves in chunks of 16, next chunk prefetched
+  // ---- Gram matrix: rows split over the four waves in chunks of 16, next chunk prefetched.
+  // Every load is unconditional (out-of-range rows read row 0, a column beyond nI / nJ
+  // reads column cI or cJ) and masked where it is used, so no load sits under a divergent
+  // branch and the next chunk's loads stay in flight during this chunk's MFMAs.
   V4 acc[3][2];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 2; ++j)
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
   const bool okI = col < nI, okJ = col < nJ;
-  const cplx<T>* __restrict__ wI = W + (size_t)(cI + (okI ? col : 0)) * R;
-  const cplx<T>* __restrict__ wJ = W + (size_t)(cJ + (okJ ? col : 0)) * R;
-  cplx<T> xi[4], xj[4], ni[4], nj[4];
-  auto load_chunk = [&](int r0, cplx<T>(&a)[4], cplx<T>(&b)[4]) {
-    const int rbase = r0 + grp * 4;
-    if (rbase + 3 < R) {
-      // 4 consecutive complex entries; 16-byte aligned (R is even, rbase a multiple of 4)
-      load4<T>(okI, wI + rbase, a);
-      load4<T>(okJ, wJ + rbase, b);
-    } else {
+  const uint32_t baseI = (uint32_t)(cI + (okI ? col : 0)) * (uint32_t)R;
+  const uint32_t baseJ = (uint32_t)(cJ + (okJ ? col : 0)) * (uint32_t)R;
+  // Rows rbase .. rbase + 3 of the lane's I and J columns.  For even R (every theta: its
+  // row count is twice a bond dimension) they are two 16-byte-aligned pairs, an
+  // out-of-range pair reading rows 0 and 1; for odd R (a general batched SVD) one load per
+  // row, an out-of-range row reading row 0.  Rows at or beyond R are masked where used.
+  // The two loops are separate instantiations, chosen once per workgroup.
+  auto gram_rows = [&](auto even_tag) {
+    constexpr bool kEven = decltype(even_tag)::value;
+    cplx<T> xi[4], xj[4], ni[4], nj[4];
+    auto load_chunk = [&](int r0, cplx<T>(&a)[4], cplx<T>(&b)[4]) {
+      const int rbase = r0 + grp * 4;
+      if constexpr (kEven) {
+        const uint32_t o0 = rbase < R ? rbase : 0, o1 = rbase + 2 < R ? rbase + 2 : 0;
+        gload_pair<T>(W, baseI + o0, a[0], a[1]);
+        gload_pair<T>(W, baseI + o1, a[2], a[3]);
+        gload_pair<T>(W, baseJ + o0, b[0], b[1]);
+        gload_pair<T>(W, baseJ + o1, b[2], b[3]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const uint32_t o = rbase + t < R ? rbase + t : 0;
+          a[t] = gload<T>(gat<T>(W, baseI + o));
+          b[t] = gload<T>(gat<T>(W, baseJ + o));
+        }
+      }
+    };
+    auto gram_chunk = [&](int r0, const cplx<T>(&a)[4], const cplx<T>(&b)[4]) {
+      const int rbase = r0 + grp * 4;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int r = rbase + t;
-        const bool ok = r < R;
-        a[t] = (okI && ok) ? wI[r] : czero<T>();
-        b[t] = (okJ && ok) ? wJ[r] : czero<T>();
+        const bool vr = rbase + t < R;
+        const cplx<T> x = cmask<T>(a[t], okI && vr), y = cmask<T>(b[t], okJ && vr);
+        gram_mfma<T>(acc[0], x, x);
+        gram_mfma<T>(acc[1], x, y);
+        gram_mfma<T>(acc[2], y, y);
+      }
+    };
+    // The prefetch is unconditional (a wave's last chunk re-reads itself, from cache): a
+    // load under a branch would make the compiler wait for it before this chunk's products.
+    int r0 = wave * 16;
+    if (r0 < R) load_chunk(r0, xi, xj);
+    for (; r0 < R; r0 += 64) {
+      load_chunk(r0 + 64 < R ? r0 + 64 : r0, ni, nj);
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+      gram_chunk(r0, xi, xj);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        xi[t] = ni[t];
+        xj[t] = nj[t];
       }
     }
   };
-  int r0 = wave * 16;
-  if (r0 < R) load_chunk(r0, xi, xj);
-  for (; r0 < R; r0 += 64) {
-    if (r0 + 64 < R) load_chunk(r0 + 64, ni, nj);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      gram_mfma<T>(acc[0], xi[t], xi[t]);
-      gram_mfma<T>(acc[1], xi[t], xj[t]);
-      gram_mfma<T>(acc[2], xj[t], xj[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      xi[t] = ni[t];
-      xj[t] = nj[t];
-    }
-  }
+  if (R & 1)
+    gram_rows(std::false_type{});
+  else
+    gram_rows(std::true_type{});
   if (wave < 2) {
     cplx<T>* p = wave == 0 ? part0 : part1;
     for (int tl = 0; tl < 3; ++tl)
@@ -387,12 +419,9 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   const bool rotate = mx > tol_scale * sqrt((double)R);
   if (tid == 0) {
     atomicMax(&out.offbits[g], __float_as_uint((float)mx));
-    atomicAdd(&out.work[0], (unsigned long long)R);
-    atomicAdd(&out.work[2], 1ull);
-    if (rotate) {
-      atomicAdd(&out.work[1], (unsigned long long)(R + (V != nullptr ? C : 0)));
-      atomicAdd(&out.work[3], 1ull);
-    }
+    uint32_t* wk = out.work + ((size_t)g * out.nslot + blockIdx.x) * 2;  // this pair's slot
+    atomicAdd(wk, 1u);
+    if (rotate) atomicAdd(wk + 1, 1u);
   }
   if (!rotate) return;  // uniform: every thread read the same red[]
 
@@ -410,19 +439,21 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   // G and Q are stored in tournament-slot order: in every round slot k is paired with slot
   // 31 - k, and thread (ia, ib) owns rows (ia, 31 - ia) and columns (ib, 31 - ib).  The
   // circle method moves every player except player 0 down one slot per round, so each
-  // thread writes its rotated 2x2 block straight to the next round's slots (double
-  // buffers); 16 consecutive lanes then always touch 16 consecutive complex entries, which
-  // keeps the interleaved LDS accesses free of bank conflicts.  After the 31 rounds of a
-  // sweep the slots are back in natural order.  A round's 16 rotations are computed once,
-  // by lanes 0..15 of wave 0 in FP64, and handed to every thread through LDS.
-  cplx<T>(*Gc)[33] = G;
-  cplx<T>(*Gn)[33] = G2;
-  cplx<T>(*Qc)[33] = Q;
-  cplx<T>(*Qn)[33] = Q2;
+  // thread writes its rotated 2x2 block straight to the next round's slots; 16 consecutive
+  // lanes then always touch 16 consecutive complex entries, which keeps the interleaved LDS
+  // accesses free of bank conflicts.  After the 31 rounds of a sweep the slots are back in
+  // natural order.  The update is in place: every thread holds its block in registers
+  // across the barrier that publishes the round's rotations, so no thread overwrites an
+  // entry another has still to read, and G and Q need one copy each (half the LDS of a
+  // double-buffered scheme, twice the workgroups per CU).  Thread (k, k) holds exactly the
+  // 2x2 block of pair k (G_pp, G_pq, G_qq), computes that pair's rotation in FP64 from its
+  // registers and hands it to every thread through LDS; the 16 such threads are spread over
+  // the four waves.
   const int ia = tid >> 4, ib = tid & 15;
   const int ra = ia, rb2 = 31 - ia, ca0 = ib, cb2 = 31 - ib;
   auto next_slot = [](int s) { return s >= 2 ? s - 1 : (s == 1 ? 31 : 0); };
   const int nra = next_slot(ra), nrb = next_slot(rb2), nca = next_slot(ca0), ncb = next_slot(cb2);
+  const bool diag_owner = ia == ib;
   // Another inner sweep follows only while the last one still rotated a pair whose cosine
   // exceeded inner_repeat: cyclic Jacobi converges quadratically, so after a sweep whose
   // largest rotated cosine was c the remaining ones are of order c^2.
@@ -431,25 +462,24 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     if (tid == 0) rmax_bits = 0u;
     __syncthreads();
     for (int rd = 0; rd < 31; ++rd) {
-      if (tid < 16) {
-        const int p = tid, q = 31 - tid;
+      const cplx<T> b00 = G[ra][ca0], b01 = G[ra][cb2], b10 = G[rb2][ca0], b11 = G[rb2][cb2];
+      const cplx<T> q00 = Q[ra][ca0], q01 = Q[ra][cb2], q10 = Q[rb2][ca0], q11 = Q[rb2][cb2];
+      if (diag_owner) {
         double c, sr, si;
-        const double gpp = (double)Gc[p][p].re, gqq = (double)Gc[q][q].re;
-        const double gr = (double)Gc[p][q].re, gi = (double)Gc[p][q].im;
+        const double gpp = (double)b00.re, gqq = (double)b11.re;
+        const double gr = (double)b01.re, gi = (double)b01.im;
         if (jacobi_rotation(gpp, gqq, gr, gi, inner_tol, c, sr, si)) {
           const double ab = gpp * gqq;
           const float cosv = ab > 0.0 ? (float)sqrt((gr * gr + gi * gi) / ab) : 3.0e38f;
           atomicMax(&rmax_bits, __float_as_uint(cosv));
         }
-        P[tid][0] = (T)c;
-        P[tid][1] = (T)sr;
-        P[tid][2] = (T)si;
+        P[ia][0] = (T)c;
+        P[ia][1] = (T)sr;
+        P[ia][2] = (T)si;
       }
       __syncthreads();
       const T ca = P[ia][0], sar = P[ia][1], sai = P[ia][2];
       const T cb = P[ib][0], sbr = P[ib][1], sbi = P[ib][2];
-      const cplx<T> b00 = Gc[ra][ca0], b01 = Gc[ra][cb2], b10 = Gc[rb2][ca0], b11 = Gc[rb2][cb2];
-      const cplx<T> q00 = Qc[ra][ca0], q01 = Qc[ra][cb2], q10 = Qc[rb2][ca0], q11 = Qc[rb2][cb2];
       // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
       cplx<T> x00, x01, x10, x11;
       x00.re = cb * b00.re - (sbr * b01.re + sbi * b01.im);
@@ -480,23 +510,16 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
       m01.im = (sbr * q00.im + sbi * q00.re) + cb * q01.im;
       m11.re = (sbr * q10.re - sbi * q10.im) + cb * q11.re;
       m11.im = (sbr * q10.im + sbi * q10.re) + cb * q11.im;
-      Gn[nra][nca] = n00;
-      Gn[nra][ncb] = n01;
-      Gn[nrb][nca] = n10;
-      Gn[nrb][ncb] = n11;
-      Qn[ra][nca] = m00;
-      Qn[ra][ncb] = m01;
-      Qn[rb2][nca] = m10;
-      Qn[rb2][ncb] = m11;
+      G[nra][nca] = n00;
+      G[nra][ncb] = n01;
+      G[nrb][nca] = n10;
+      G[nrb][ncb] = n11;
+      Q[ra][nca] = m00;
+      Q[ra][ncb] = m01;
+      Q[rb2][nca] = m10;
+      Q[rb2][ncb] = m11;
       __syncthreads();
-      cplx<T>(*tg)[33] = Gc;
-      Gc = Gn;
-      Gn = tg;
-      cplx<T>(*tq)[33] = Qc;
-      Qc = Qn;
-      Qn = tq;
     }
-    __syncthreads();
     const float rmax = __uint_as_float(rmax_bits);
     if (!(rmax > (float)inner_repeat) || rmax_bits == 0u) break;
   }
@@ -507,10 +530,10 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   if (tid < 32) {
     int p = tid;
     if (sort_pairs && nI == 16 && nJ == 16) {
-      const T dj = Gc[tid][tid].re;
+      const T dj = G[tid][tid].re;
       int rank = 0;
       for (int i = 0; i < 32; ++i) {
-        const T di = Gc[i][i].re;
+        const T di = G[i][i].re;
         rank += (di > dj || (di == dj && i < tid)) ? 1 : 0;
       }
       p = (I < J) ? rank : (rank < 16 ? rank + 16 : rank - 16);
@@ -518,11 +541,11 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
     pos[tid] = p;
   }
   __syncthreads();
-  // column-permuted copy of Q in the free G buffer
-  cplx<T>(*Qp)[33] = Gn;
+  // column-permuted copy of Q in G, which is no longer needed
+  cplx<T>(*Qp)[33] = G;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
-    Qp[i][pos[j]] = Qc[i][j];
+    Qp[i][pos[j]] = Q[i][j];
   }
   __syncthreads();
 
@@ -530,49 +553,59 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
   // next 16-row chunk prefetched
   const int npass = V != nullptr ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
-    cplx<T>* __restrict__ M = pass == 0 ? W : V;
+    const gptr<cplx<T>> __restrict__ M = pass == 0 ? W : V;
     const int rows = pass == 0 ? R : C;
+    // element offsets of this lane's 8 k-slice columns; a column beyond nI / nJ reads
+    // column cI (masked where used), an out-of-range row reads row 0
+    uint32_t coff[8];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const int kk = ks * 4 + grp;
+      const bool ok = kk < 16 ? kk < nI : kk - 16 < nJ;
+      coff[ks] = (uint32_t)(ok ? (kk < 16 ? cI + kk : cJ + kk - 16) : cI) * (uint32_t)rows;
+    }
     cplx<T> av[8], an[8];
     auto load_rows = [&](int rbase, cplx<T>(&dst)[8]) {
       const int r = rbase + col;
+      const uint32_t rr = r < rows ? r : 0;
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        const int kk = ks * 4 + grp;
-        const bool ok = (kk < 16 ? kk < nI : kk - 16 < nJ) && r < rows;
-        const int cidx = kk < 16 ? cI + kk : cJ + kk - 16;
-        dst[ks] = ok ? M[(size_t)cidx * rows + r] : czero<T>();
-      }
+      for (int ks = 0; ks < 8; ++ks) dst[ks] = gload<T>(gat<T>(M, coff[ks] + rr));
     };
     int rb = wave * 16;
     if (rb < rows) load_rows(rb, av);
     for (; rb < rows; rb += 64) {
-      if (rb + 64 < rows) load_rows(rb + 64, an);
+      load_rows(rb + 64 < rows ? rb + 64 : rb, an);  // unconditional, as in the Gram loop
+      __builtin_amdgcn_sched_barrier(0);
+      const bool rok = rb + col < rows;
       V4 o[2][2];
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
           for (int v = 0; v < 4; ++v) o[i][j][v] = T(0);
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
-        const cplx<T> b0 = Qp[ks * 4 + grp][col];
-        const cplx<T> b1 = Qp[ks * 4 + grp][16 + col];
-        cmfma<T>(o[0], av[ks], b0);
-        cmfma<T>(o[1], av[ks], b1);
+        const int kk = ks * 4 + grp;
+        const bool ok = rok && (kk < 16 ? kk < nI : kk - 16 < nJ);
+        const cplx<T> a = cmask<T>(av[ks], ok);
+        const cplx<T> b0 = Qp[kk][col];
+        const cplx<T> b1 = Qp[kk][16 + col];
+        cmfma<T>(o[0], a, b0);
+        cmfma<T>(o[1], a, b1);
       }
       for (int jt = 0; jt < 2; ++jt) {
         const int jj = jt * 16 + col;
         const bool okc = jt == 0 ? jj < nI : jj - 16 < nJ;
         const int cidx = jt == 0 ? cI + jj : cJ + jj - 16;
         if (!okc) continue;
-        cplx<T>* __restrict__ dst = M + (size_t)cidx * rows;
+        const gptr<cplx<T>> __restrict__ dst = gat<T>(M, (uint32_t)cidx * (uint32_t)rows);
         if constexpr (sizeof(T) == 4) {
           // f32 layout: this lane's four values are rows rb + 4*grp + 0..3 of one column
           const int r4 = rb + 4 * grp;
           if (r4 + 3 < rows) {
-            float4 u, w;
+            vf4 u, w;
             u.x = o[jt][0][0]; u.y = o[jt][1][0]; u.z = o[jt][0][1]; u.w = o[jt][1][1];
             w.x = o[jt][0][2]; w.y = o[jt][1][2]; w.z = o[jt][0][3]; w.w = o[jt][1][3];
-            *reinterpret_cast<float4*>(dst + r4) = u;
-            *reinterpret_cast<float4*>(dst + r4 + 2) = w;
+            *reinterpret_cast<gptr<vf4>>(dst + r4) = u;
+            *reinterpret_cast<gptr<vf4>>(dst + r4 + 2) = w;
             continue;
           }
         }
@@ -582,7 +615,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const GateDesc* __res
             cplx<T> z;
             z.re = o[jt][0][v];
             z.im = o[jt][1][v];
-            dst[rr] = z;
+            gstore<T>(dst + rr, z);
           }
         }
       }
@@ -620,7 +653,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
   const int g = blockIdx.x;
   const GateDesc* d = descs + g;
   const int R = d->R, C = d->C;
-  const cplx<T>* __restrict__ W = (const cplx<T>*)d->w;
+  const gptr<const cplx<T>> __restrict__ W = as_global((const cplx<T>*)d->w);
   __shared__ double key[1024];
   __shared__ int idx[1024];
   __shared__ double red_d[4];
@@ -632,7 +665,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
   for (int j = wave; j < C; j += 4) {
     double s = 0.0;
     for (int r = lane; r < R; r += 64) {
-      const cplx<T> x = W[(size_t)j * R + r];
+      const cplx<T> x = gload<T>(W + ((size_t)j * R + r));
       s += (double)x.re * (double)x.re + (double)x.im * (double)x.im;
     }
     s = wave_sum(s);
@@ -695,7 +728,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
   if (d->eps_mode == 1) eps = discarded / total;
   if (d->eps_mode == 2) eps = 1.0 - (total - discarded);
   const double nu = d->stabilize ? 1.0 / sqrt(1.0 - eps) : 1.0;
-  double* lam_m = d->lam_m;
+  const gptr<double> lam_m = as_global(d->lam_m);
   for (int j = tid; j < C; j += 256) {
     const double s = sqrt(fmax(key[j], 0.0));
     out.sig[(size_t)g * out.cmax + j] = s;
@@ -728,35 +761,35 @@ __global__ __launch_bounds__(256) void writeback_kernel(const GateDesc* __restri
   const int cl = d->cl, cr = d->cr, R = d->R, C = d->C, transposed = d->transposed;
   const double* __restrict__ sig = out.sig + (size_t)g * out.cmax;
   const int* __restrict__ perm = out.perm + (size_t)g * out.cmax;
-  const cplx<T>* __restrict__ W = (const cplx<T>*)d->w;
-  const cplx<T>* __restrict__ V = (const cplx<T>*)d->v;
+  const gptr<const cplx<T>> __restrict__ W = as_global((const cplx<T>*)d->w);
+  const gptr<const cplx<T>> __restrict__ V = as_global((const cplx<T>*)d->v);
   const int tid = threadIdx.x;
   if (blockIdx.z == 0) {
-    const cplx<T>* __restrict__ L = transposed ? V : W;
+    const gptr<const cplx<T>> __restrict__ L = transposed ? V : W;
     const int ldl = transposed ? C : R;
     const bool divsig = !transposed;
-    const double* __restrict__ lam_l = d->lam_l;
-    cplx<T>* __restrict__ gout = (cplx<T>*)d->gq;
+    const gptr<const double> __restrict__ lam_l = as_global(d->lam_l);
+    const gptr<cplx<T>> __restrict__ gout = as_global((cplx<T>*)d->gq);
     const size_t total = 2 * (size_t)cl * k;
     for (size_t e = (size_t)blockIdx.x * 256 + tid; e < total; e += (size_t)gridDim.x * 256) {
       const int a = (int)(e % cl);
       const size_t rest = e / cl;
       const int j = (int)(rest % k), sp = (int)(rest / k);
-      const cplx<T> x = L[(size_t)perm[j] * ldl + sp * cl + a];
+      const cplx<T> x = gload<T>(L + ((size_t)perm[j] * ldl + sp * cl + a));
       double sc = 1.0 / lam_l[a];
       if (divsig) sc /= sig[j];
       cplx<T> z;
       z.re = (T)((double)x.re * sc);
       z.im = (T)((double)x.im * sc);
-      gout[(size_t)sp * cl * k + (size_t)j * cl + a] = z;
+      gstore<T>(gout + ((size_t)sp * cl * k + (size_t)j * cl + a), z);
     }
   } else {
     __shared__ cplx<T> tile[32][33];
-    const cplx<T>* __restrict__ Rs = transposed ? W : V;
+    const gptr<const cplx<T>> __restrict__ Rs = transposed ? W : V;
     const int ldr = transposed ? R : C;
     const bool divsig = transposed;
-    const double* __restrict__ lam_r = d->lam_r;
-    cplx<T>* __restrict__ gout = (cplx<T>*)d->gq1;
+    const gptr<const double> __restrict__ lam_r = as_global(d->lam_r);
+    const gptr<cplx<T>> __restrict__ gout = as_global((cplx<T>*)d->gq1);
     const int tj = (k + 31) >> 5, tc = (cr + 31) >> 5;
     const int ntiles = 2 * tj * tc;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -767,7 +800,7 @@ __global__ __launch_bounds__(256) void writeback_kernel(const GateDesc* __restri
         const int jj = e >> 5, cc = e & 31;
         const int j = j0 + jj, c = c0 + cc;
         if (j < k && c < cr) {
-          const cplx<T> x = Rs[(size_t)perm[j] * ldr + tp * cr + c];
+          const cplx<T> x = gload<T>(Rs + ((size_t)perm[j] * ldr + tp * cr + c));
           double sc = 1.0 / lam_r[c];
           if (divsig) sc /= sig[j];
           cplx<T> z;
@@ -781,7 +814,7 @@ __global__ __launch_bounds__(256) void writeback_kernel(const GateDesc* __restri
         const int e = tid + 256 * i;
         const int jj = e & 31, cc = e >> 5;
         const int j = j0 + jj, c = c0 + cc;
-        if (j < k && c < cr) gout[(size_t)tp * k * cr + (size_t)c * k + j] = tile[jj][cc];
+        if (j < k && c < cr) gstore<T>(gout + ((size_t)tp * k * cr + (size_t)c * k + j), tile[jj][cc]);
       }
       __syncthreads();
     }
