@@ -45,10 +45,12 @@ __device__ inline double rcp_f64(double x) {
 // Jacobi rotation of the Hermitian 2x2 block [[a, g], [conj(g), b]] in FP64 (the symmetric
 // Schur step with the phase of g factored out): J = [[c, s], [-conj(s), c]] with
 // zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
-// s = t c g/|g|; J^H [[a, g], [conj g, b]] J is diagonal.  Identity when
-// |g| <= thr * sqrt(a b) or g = 0.  For |zeta| > 1e100 (a rounding residue rotated against
-// a large column), t = 1 / (2|zeta|), which is exact to double precision and avoids the
-// overflow of 1 + zeta^2.  Returns whether a rotation is applied.
+// s = t c g/|g|; J^H [[a, g], [conj g, b]] J is diagonal.  With d = |b - a| and
+// S = sqrt(d^2 + 4|g|^2) the same rotation is c = sqrt((d + S) / (2S)) and
+// s = sign(b - a) g sqrt(2 / (S (d + S))) (sign +1 for b = a), which takes one square root
+// and one reciprocal square root, no division, and stays finite for |g| far below |b - a|.
+// A block whose entries lie outside [1e-140, 1e140] is first scaled by 2^(+-600) (exact) so
+// that d^2 + 4|g|^2 stays a normal number.  Identity when |g| <= thr * sqrt(a b) or g = 0.
 __device__ inline bool jacobi_rotation(double a, double b, double gr, double gi, double thr,
                                        double& c, double& sr, double& si) {
   const double g2 = gr * gr + gi * gi;
@@ -56,15 +58,22 @@ __device__ inline bool jacobi_rotation(double a, double b, double gr, double gi,
   sr = 0.0;
   si = 0.0;
   if (!(g2 > 0.0) || g2 <= thr * thr * fmax(a * b, 0.0)) return false;
-  const double rg = rsqrt_f64(g2);  // 1 / |g|
-  const double zeta = 0.5 * (b - a) * rg;
-  const double az = fabs(zeta);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) *
-                   (az > 1e100 ? 0.5 / az : rcp_f64(az + sqrt(1.0 + az * az)));
-  c = rsqrt_f64(1.0 + t * t);
-  const double sc = t * c * rg;
-  sr = sc * gr;
-  si = sc * gi;
+  double d = fabs(b - a), xr = gr, xi = gi;
+  const double m = fmax(d, fmax(fabs(gr), fabs(gi)));
+  if (m < 1e-140 || m > 1e140) {
+    const double f = m < 1e-140 ? 0x1p600 : 0x1p-600;
+    d *= f;
+    xr *= f;
+    xi *= f;
+  }
+  const double dd = fma(d, d, 4.0 * (xr * xr + xi * xi));
+  const double S = dd * rsqrt_f64(dd);
+  const double e = d + S;
+  const double sf = rsqrt_f64(0.5 * S * e);
+  c = 0.5 * e * sf;
+  const double ss = b >= a ? sf : -sf;
+  sr = ss * xr;
+  si = ss * xi;
   return true;
 }
 
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   __shared__ cplx<T> Q[32][33];
   __shared__ T P[16][4];  // one round's rotations: c, Re s, Im s
   __shared__ double red[4];
-  __shared__ unsigned int rmax_bits;  // largest |g| / sqrt(a b) rotated in this inner sweep
+  __shared__ unsigned int rmax_bits;  // largest |g|^2 / (a b) rotated in this inner sweep
   __shared__ int pos[32];
   // reduction scratch: wave w < 2 owns region w (3 tiles of 16 x 16), aliasing G / Q
   cplx<T>* part0 = &G[0][0];
@@ -469,9 +478,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
         const double gpp = (double)b00.re, gqq = (double)b11.re;
         const double gr = (double)b01.re, gi = (double)b01.im;
         if (jacobi_rotation(gpp, gqq, gr, gi, inner_tol, c, sr, si)) {
+          // squared cosine |g|^2 / (a b) of the rotated pair (a threshold test only: the
+          // hardware reciprocal estimate is accurate enough)
           const double ab = gpp * gqq;
-          const float cosv = ab > 0.0 ? (float)sqrt((gr * gr + gi * gi) / ab) : 3.0e38f;
-          atomicMax(&rmax_bits, __float_as_uint(cosv));
+          const float cos2 =
+              ab > 0.0 ? (float)((gr * gr + gi * gi) * __builtin_amdgcn_rcp(ab)) : 3.0e38f;
+          atomicMax(&rmax_bits, __float_as_uint(cos2));
         }
         P[ia][0] = (T)c;
         P[ia][1] = (T)sr;
@@ -520,8 +532,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
       Q[rb2][ncb] = m11;
       __syncthreads();
     }
-    const float rmax = __uint_as_float(rmax_bits);
-    if (!(rmax > (float)inner_repeat) || rmax_bits == 0u) break;
+    const float rmax2 = __uint_as_float(rmax_bits);
+    if (!(rmax2 > (float)(inner_repeat * inner_repeat)) || rmax_bits == 0u) break;
   }
   __syncthreads();
   // Optional ordering of the pair's 32 new columns by norm: the 16 largest go to the
