@@ -26,19 +26,14 @@ __device__ inline int rr32(int slot, int round) {
   return slot == 0 ? 0 : 1 + x;
 }
 
-// FP64 reciprocal square root and reciprocal: hardware estimate refined by two Newton
-// steps (each doubles the number of correct bits), for positive finite arguments.
+// FP64 reciprocal square root for positive finite arguments: the hardware estimate (relative
+// error 2^-24 on gfx950, measured) refined by NEWTON Newton steps, each of which doubles the
+// number of correct bits: one step gives 2^-47, two give full double precision.
+template <int NEWTON>
 __device__ inline double rsqrt_f64(double x) {
   double y = __builtin_amdgcn_rsq(x);
-  y = y * (1.5 - 0.5 * x * y * y);
-  y = y * (1.5 - 0.5 * x * y * y);
-  return y;
-}
-
-__device__ inline double rcp_f64(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * (2.0 - x * y);
-  y = y * (2.0 - x * y);
+#pragma unroll
+  for (int i = 0; i < NEWTON; ++i) y = y * (1.5 - 0.5 * x * y * y);
   return y;
 }
 
@@ -51,6 +46,9 @@ __device__ inline double rcp_f64(double x) {
 // and one reciprocal square root, no division, and stays finite for |g| far below |b - a|.
 // A block whose entries lie outside [1e-140, 1e140] is first scaled by 2^(+-600) (exact) so
 // that d^2 + 4|g|^2 stays a normal number.  Identity when |g| <= thr * sqrt(a b) or g = 0.
+// NEWTON: refinement steps of the reciprocal square roots (2 for rotations applied in FP64;
+// 1 is exact to 2^-47, ample for rotations rounded to FP32).
+template <int NEWTON>
 __device__ inline bool jacobi_rotation(double a, double b, double gr, double gi, double thr,
                                        double& c, double& sr, double& si) {
   const double g2 = gr * gr + gi * gi;
@@ -67,9 +65,9 @@ __device__ inline bool jacobi_rotation(double a, double b, double gr, double gi,
     xi *= f;
   }
   const double dd = fma(d, d, 4.0 * (xr * xr + xi * xi));
-  const double S = dd * rsqrt_f64(dd);
+  const double S = dd * rsqrt_f64<NEWTON>(dd);
   const double e = d + S;
-  const double sf = rsqrt_f64(0.5 * S * e);
+  const double sf = rsqrt_f64<NEWTON>(0.5 * S * e);
   c = 0.5 * e * sf;
   const double ss = b >= a ? sf : -sf;
   sr = ss * xr;
@@ -477,7 +475,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
         double c, sr, si;
         const double gpp = (double)b00.re, gqq = (double)b11.re;
         const double gr = (double)b01.re, gi = (double)b01.im;
-        if (jacobi_rotation(gpp, gqq, gr, gi, inner_tol, c, sr, si)) {
+        if (jacobi_rotation<sizeof(T) == 4 ? 1 : 2>(gpp, gqq, gr, gi, inner_tol, c, sr, si)) {
           // squared cosine |g|^2 / (a b) of the rotated pair (a threshold test only: the
           // hardware reciprocal estimate is accurate enough)
           const double ab = gpp * gqq;
