@@ -37,27 +37,35 @@ def _two_site(gq, lam_l, lam_m, gq1, lam_r):
     return np.einsum("asm,mtc->astc", a, b)
 
 
+@pytest.mark.parametrize("reading", ["literal", "complement"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_full_size_layer_sampled_bonds(saturated, precision):
+def test_full_size_layer_sampled_bonds(saturated, precision, reading):
+    """Both eps readings: literal is the library default, complement the benchmark's."""
     g, l, bonds, gates = saturated
     m = ptebd.MPS(N, CHI, precision)
-    say(f"import ({precision})")
+    say(f"import ({precision}, {reading})")
     m.import_state(g, l)
     say(f"apply one layer of {len(bonds)} gates ({precision})")
-    st = m.apply_layer(bonds, gates, chi_max=CHI, cutoff=1e-12)
+    st = m.apply_layer(bonds, gates, chi_max=CHI, cutoff=1e-12, eps_reading=reading)
     assert st["n_unconverged"] == 0
     tol = TOL[precision]
     for q in SAMPLED:
         i = int(np.where(bonds == q)[0][0])
         local = po.VidalMPS([g[q], g[q + 1]], [l[q], l[q + 1], l[q + 2]])
         ref = po.bond_update(local, 0, gates[i], CHI, oracle_cutoff(1e-12, precision),
-                             stabilize=True)
+                             stabilize=True, eps_reading=reading)
         say(f"  q={q}: theta {2 * len(l[q])}x{2 * len(l[q + 2])}, k={ref['k']}")
         assert st["k"][i] == ref["k"]
         s1 = ref["sigma"][0]
         lam_gpu = m.get_lambda(q + 1)
-        assert np.max(np.abs(lam_gpu - local.lam[1])) <= tol["lam"] * s1
-        assert abs(st["eps"][i] - ref["eps"]) <= tol["eps"] * s1 ** 2 * 10
+        # relative to the largest new Schmidt value nu sigma_1 (the complement reading
+        # rescales this unnormalized synthetic state's sigma by nu = 1/|kept sigma|)
+        assert np.max(np.abs(lam_gpu - local.lam[1])) <= tol["lam"] * local.lam[1][0]
+        if reading == "literal":
+            assert abs(st["eps"][i] - ref["eps"]) <= tol["eps"] * s1 ** 2 * 10
+        else:
+            # eps = 1 - sum of the kept sigma^2: |d eps| <= 2 sum_j sigma_j |d sigma_j|
+            assert abs(st["eps"][i] - ref["eps"]) <= 2 * tol["lam"] * s1 * float(np.sum(ref["sigma"]))
         th_ref = _two_site(local.gam[0], l[q], local.lam[1], local.gam[1], l[q + 2])
         th_gpu = _two_site(m.export_site(q), l[q], lam_gpu, m.export_site(q + 1), l[q + 2])
         err = np.linalg.norm(th_gpu - th_ref) / np.linalg.norm(th_ref)
