@@ -170,15 +170,17 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
                       int ptsu_steps, int flags, ptebd_layer_stats* stats);
 
 /* Restore the canonical form of state s: the Canonicalize step of Algorithm 1, done before
- * measuring or sampling.  A left-to-right sweep of tSU steps on the pairs (0,1), (1,2), ...,
- * (N-2,N-1), then a right-to-left sweep back (each tSU as in ptebd_ptsu: identity gate
- * skipped, cutoff only, nu = 1), then the normalization Lambda[i] /= n on the inner bonds
- * and Gamma[q] *= n on the inner sites, n the norm (n^2 = sum Lambda[1]^2 once canonical).
+ * measuring or sampling.  tSU steps (as in ptebd_ptsu: identity gate skipped, cutoff
+ * only, nu = 1) sweep from both ends to the middle bond m = (N-2)/2 -- the pairs (0,1),
+ * (1,2), .. up to m and (N-2,N-1), (N-3,N-2), .. down to m, two per batch -- then one tSU at
+ * m, then sweeps from the middle back out to both ends; then the normalization
+ * Lambda[i] /= n on the inner bonds and Gamma[q] *= n on the inner sites, n the norm
+ * (n^2 = sum Lambda[1]^2 once canonical).
  * Afterwards the state has unit norm and satisfies the canonical conditions of Eq.
  * (l_r_cano); bond dimensions can only shrink (values <= cutoff * sigma_1 are dropped; the
- * FP32 floor applies).  norm_out (may be NULL) receives n.  The 2(N-1) bond updates run one
- * after another: the cost is sequential in N, unlike a layer.  The norm and fidelity
- * estimates are left unchanged.
+ * FP32 floor applies).  norm_out (may be NULL) receives n.  The 2N-3 bond updates run in
+ * about N sequential batches: the cost is sequential in N, unlike a layer.  The norm and
+ * fidelity estimates are left unchanged.
  * Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV. */
 int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out);
 

@@ -834,14 +834,33 @@ int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out) {
   PT_CHECK(set_device(h));
   const int n = h->st[s].n;
   int n_unconv = 0;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int t = 0; t + 1 < n; ++t) {
-      const int q = pass == 0 ? t : n - 2 - t;
-      std::vector<Item> items{Item{s, q, nullptr, 0}};
-      UpdateResult res;
-      PT_CHECK(run_updates_dispatch(h, items, cutoff, 0, 0, &res));
-      n_unconv += res.n_unconverged;
-    }
+  // Sweeps from both ends.  Bonds q = 0 .. n-2 (a tSU at q acts on sites q, q+1); m is the
+  // middle bond.  Pass 1 sweeps q = 0, 1, .., m-1 (left block left-canonical) and, in the
+  // same batch, q = n-2, n-3, .., m+1 (right block right-canonical); the tSU at m then sees
+  // identity environments on both sides and gives the exact Schmidt decomposition there;
+  // pass 2 sweeps q = m-1, .., 0 and q = m+1, .., n-2 together.  The two items of a batch
+  // act on disjoint sites and share only a read of Lambda[m+1]; a tSU inside one block only
+  // regauges that block's interior, so the other block's environment stays the identity.
+  // About n sequential steps instead of the 2(n-1) of one sweep there and one back.
+  const int m = (n - 2) / 2;
+  auto step = [&](int ql, int qr) -> int {
+    std::vector<Item> items;
+    if (ql >= 0) items.push_back(Item{s, ql, nullptr, 0});
+    if (qr >= 0) items.push_back(Item{s, qr, nullptr, 0});
+    if (items.empty()) return PTEBD_OK;
+    UpdateResult res;
+    PT_CHECK(run_updates_dispatch(h, items, cutoff, 0, 0, &res));
+    n_unconv += res.n_unconverged;
+    return PTEBD_OK;
+  };
+  if (n >= 2) {
+    const int span = std::max(m, n - 2 - m);
+    for (int t = 0; t < span; ++t)
+      PT_CHECK(step(t < m ? t : -1, n - 2 - t > m ? n - 2 - t : -1));
+    PT_CHECK(step(m, -1));
+    for (int t = 0; t < span; ++t)
+      PT_CHECK(step(m - 1 - t >= 0 ? m - 1 - t : -1, m + 1 + t <= n - 2 ? m + 1 + t : -1));
+  }
   const StateInfo& si = h->st[s];
   // in canonical form every bond carries the whole norm: n^2 = sum Lambda[1]^2
   std::vector<double> l1(si.dims[1]);
