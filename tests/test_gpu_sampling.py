@@ -27,11 +27,13 @@ def _truncated_state(n, chi, depth, seed, precision, ptsu=0):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("n,chi,depth", [(12, 8, 10), (40, 32, 14), (2, 2, 3)])
+@pytest.mark.parametrize("n,chi,depth", [(12, 8, 10), (13, 8, 10), (40, 32, 14), (2, 2, 3),
+                                         (3, 2, 4)])
 def test_canonicalize_matches_oracle(precision, n, chi, depth):
     """A truncated (non-canonical) Haar-circuit state: after canonicalize, Schmidt values equal
     the oracle's sequential-SVD canonicalization of the same (exported) state, the state is the
-    same up to its norm, and the canonical distance (Eq. (dist_to_cano)) vanishes."""
+    same up to its norm, and the canonical distance (Eq. (dist_to_cano)) vanishes.  The library
+    sweeps from both ends; odd N (13, 3) gives halves of different lengths."""
     tol = TOL[precision]
     m, ref = _truncated_state(n, chi, depth, 1, precision)
     before = po.norm(ref)
