@@ -903,8 +903,10 @@ int ptebd_sample(ptebd_mps_t h, int s, int n_samples, const double* uniforms, ui
     if (!(uniforms[e] >= 0.0 && uniforms[e] < 1.0))
       return fail(PTEBD_EINVAL, "uniforms must lie in [0, 1)");
   PT_CHECK(set_device(h));
-  // device layout: uniforms | bits | W ping-pong | sel ping-pong | scale ping-pong | err
+  // device layout: uniforms | bits | W ping-pong | sel ping-pong | scale ping-pong | err |
+  // partial norms per sample and column tile
   const int ldw = 2 * si.cap;
+  const int max_tiles = (ldw + 31) / 32;
   const size_t wbytes = h->celem * (size_t)n_samples * ldw;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t o_u = 0, o_b = al(o_u + sizeof(double) * cnt), o_w0 = al(o_b + cnt),
@@ -912,7 +914,8 @@ int ptebd_sample(ptebd_mps_t h, int s, int n_samples, const double* uniforms, ui
                o_s1 = al(o_s0 + sizeof(int32_t) * n_samples),
                o_c0 = al(o_s1 + sizeof(int32_t) * n_samples),
                o_c1 = al(o_c0 + sizeof(double) * n_samples),
-               o_e = al(o_c1 + sizeof(double) * n_samples), total = o_e + 256;
+               o_e = al(o_c1 + sizeof(double) * n_samples), o_p = o_e + 256,
+               total = o_p + sizeof(double) * 2 * (size_t)n_samples * max_tiles;
   PT_CHECK(h->samp.ensure(total));
   char* base = (char*)h->samp.p;
   PT_HIP(hipMemcpyAsync(base + o_u, uniforms, sizeof(double) * cnt, hipMemcpyHostToDevice,
@@ -940,6 +943,8 @@ int ptebd_sample(ptebd_mps_t h, int s, int n_samples, const double* uniforms, ui
     a.bits = (uint8_t*)(base + o_b) + q;
     a.bstride = n;
     a.err = (int32_t*)(base + o_e);
+    a.part = (double*)(base + o_p);
+    a.ntiles = (2 * a.cm + 31) / 32;
     timed(pf, PTEBD_KERNEL_SAMPLE, h->stream, [&] {
       if (h->precision == PTEBD_FP64)
         ptebd::launch_sample_site<double>(a, h->stream);

@@ -95,6 +95,9 @@ struct SampleSite {
   uint8_t* bits;             // bit of this site, sample i at bits[i * bstride]
   int32_t bstride;
   int32_t* err;              // bit0: a vanishing conditional probability
+  double* part;              // per sample and column tile: partial p_0, p_1 (n_samples x
+                             // ntiles x 2)
+  int32_t ntiles;            // column tiles of 32 over the two planes: ceil(2 cm / 32)
 };
 
 // Kernel launchers (ptebd_kernels.hip).  All are asynchronous on `stream`.

@@ -1,7 +1,9 @@
 // HIP kernels of the measurement step that follows Canonicalize in Algorithm 1:
-//   sample_site_kernel -- one site of perfect sampling (Ferris and Vidal) for a batch of bit
+//   sample_contract_kernel, sample_decide_kernel
+//                      -- one site of perfect sampling (Ferris and Vidal) for a batch of bit
 //                         strings: a (samples x chi_q) by (chi_q x 2 chi_{q+1}) complex
-//                         product on MFMA, FP64 conditional probabilities and decisions
+//                         product on MFMA in 32 x 32 tiles with FP64 partial norms, then the
+//                         FP64 conditional probabilities and decisions
 //   scale_state_kernel -- the normalization of a canonical form: Lambda[i] / n on the inner
 //                         bonds, n Gamma[q] on the inner sites
 #include <algorithm>
@@ -12,102 +14,105 @@
 namespace ptebd {
 namespace {
 
-// Perfect sampling at site q for samples [16 b, 16 b + 16) (b = blockIdx.x).
-// The previous site left, per sample i, the unnormalized row W_prev[i, :] (plane 0 then
-// plane 1, cl values each), the chosen plane sel[i] and 1 / sqrt(p_sel); the prefix vector
-// is v_i = W_prev[i, sel_i cl + a] * scale_i (v_i = (1) at site 0).  This site forms
+// Perfect sampling at site q, step 1: the contraction.  The previous site left, per sample
+// i, the unnormalized row W_prev[i, :] (plane 0 then plane 1, cl values each), the chosen
+// plane sel[i] and 1 / sqrt(p_sel); the prefix vector is v_i = W_prev[i, sel_i cl + a] *
+// scale_i (v_i = (1) at site 0).  This kernel forms
 //   W[i, p cm + c] = sum_a v_i[a] Gamma[q]_{a p c} Lambda[q+1]_c          (p = 0, 1)
-// with B = Gamma Lambda right-isometric in the canonical form, p_p = sum_c |W[i, p cm + c]|^2
-// in FP64, and bit q of sample i = (u_i < p_0 / (p_0 + p_1)) ? 0 : 1.
-// Four waves; each takes groups of four 16-column output tiles; K = cl in steps of 4.
+// for a 32-sample x 32-column tile per workgroup (blockIdx.x: samples, blockIdx.y: columns
+// of the two planes), with B = Gamma Lambda right-isometric in the canonical form, and the
+// tile's partial sums of |W[i, .]|^2 over its plane-0 and plane-1 columns in FP64.  K = cl
+// is staged through LDS in steps of 16; four waves, each a 16 x 16 sub-tile on MFMA.
 template <class T>
-__global__ __launch_bounds__(256) void sample_site_kernel(SampleSite a) {
+__global__ __launch_bounds__(256) void sample_contract_kernel(SampleSite a) {
   typedef typename Mfma<T>::v4 V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wa = wave >> 1, wc = wave & 1;
   const int col = lane & 15, grp = lane >> 4;
-  const int i0 = blockIdx.x * 16;
-  const int cl = a.cl, cm = a.cm, ncols = 2 * cm;
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int cl = a.cl, cm = a.cm, ncols = 2 * cm, S = a.n_samples;
   const cplx<T>* __restrict__ G = (const cplx<T>*)a.gamma;
   const cplx<T>* __restrict__ win = (const cplx<T>*)a.w_in;
   cplx<T>* __restrict__ wout = (cplx<T>*)a.w_out;
-  __shared__ double part[4][16][2];
+  __shared__ cplx<T> As[16][33];  // [k][sample]
+  __shared__ cplx<T> Bs[16][33];  // [k][column]
+  __shared__ double red[2][32][2];  // [column half][sample][plane]
 
-  // A operand: lane supplies row `col` (sample i0 + col), k = k0 + grp
-  const int my_i = i0 + col;
-  const bool row_ok = my_i < a.n_samples;
-  const cplx<T>* __restrict__ vrow = nullptr;
-  T vscale = T(1);
-  if (row_ok && !a.first) {
-    vrow = win + (size_t)my_i * a.ldw + (size_t)a.sel_in[my_i] * cl;
-    vscale = (T)a.scale_in[my_i];
+  // each thread stages two A and two B elements per K step: k = tid & 15, row / column
+  // (tid >> 4) and (tid >> 4) + 16 of the tile
+  const int lk = tid & 15, lr = tid >> 4;
+  const cplx<T>* rowp[2];
+  T rsc[2];
+  bool rok[2];
+  int boff[2];
+  T blam[2];
+  bool cok[2];
+  for (int h = 0; h < 2; ++h) {
+    const int i = i0 + lr + 16 * h;
+    rok[h] = i < S;
+    const int ic = rok[h] ? i : 0;
+    rowp[h] = a.first ? win : win + (size_t)ic * a.ldw + (size_t)a.sel_in[ic] * cl;
+    rsc[h] = a.first ? T(1) : (T)a.scale_in[ic];
+    const int j = j0 + lr + 16 * h;
+    cok[h] = j < ncols;
+    const int p = j >= cm ? 1 : 0, c = cok[h] ? j - p * cm : 0;
+    boff[h] = p * cl * cm + c * cl;
+    blam[h] = (T)a.lam_r[c];
   }
-  double np0[4] = {0.0, 0.0, 0.0, 0.0}, np1[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int cb = wave * 64; cb < ncols; cb += 256) {
-    V4 acc[4][2];
-    for (int t = 0; t < 4; ++t)
-      for (int v = 0; v < 4; ++v) {
-        acc[t][0][v] = T(0);
-        acc[t][1][v] = T(0);
-      }
-    // B operand columns of this lane, one per tile
-    int boff[4];
-    T blam[4];
-    for (int t = 0; t < 4; ++t) {
-      const int j = cb + 16 * t + col;
-      if (j < ncols) {
-        const int p = j >= cm ? 1 : 0;
-        const int c = j - p * cm;
-        boff[t] = p * cl * cm + c * cl;
-        blam[t] = (T)a.lam_r[c];
-      } else {
-        boff[t] = -1;
-        blam[t] = T(0);
-      }
-    }
-    for (int k0 = 0; k0 < cl; k0 += 4) {
-      const int k = k0 + grp;
+  V4 acc[2];
+  for (int v = 0; v < 4; ++v) {
+    acc[0][v] = T(0);
+    acc[1][v] = T(0);
+  }
+  for (int k0 = 0; k0 < cl; k0 += 16) {
+    const int k = k0 + lk;
+    const bool kok = k < cl;
+    for (int h = 0; h < 2; ++h) {
       cplx<T> av = czero<T>();
-      if (row_ok && k < cl) {
+      if (rok[h] && kok) {
         if (a.first) {
           av.re = k == 0 ? T(1) : T(0);
         } else {
-          const cplx<T> z = vrow[k];
-          av.re = z.re * vscale;
-          av.im = z.im * vscale;
+          const cplx<T> z = rowp[h][k];
+          av.re = z.re * rsc[h];
+          av.im = z.im * rsc[h];
         }
       }
+      As[lk][lr + 16 * h] = av;
+      cplx<T> bv = czero<T>();
+      if (cok[h] && kok) {
+        const cplx<T> g = G[boff[h] + k];
+        bv.re = g.re * blam[h];
+        bv.im = g.im * blam[h];
+      }
+      Bs[lk][lr + 16 * h] = bv;
+    }
+    __syncthreads();
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        cplx<T> bv = czero<T>();
-        if (boff[t] >= 0 && k < cl) {
-          const cplx<T> g = G[boff[t] + k];
-          bv.re = g.re * blam[t];
-          bv.im = g.im * blam[t];
-        }
-        cmfma<T>(acc[t], av, bv);
-      }
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + grp;
+      cmfma<T>(acc, As[kk][wa * 16 + col], Bs[kk][wc * 16 + col]);
     }
-    for (int t = 0; t < 4; ++t) {
-      const int j = cb + 16 * t + col;
-      if (j >= ncols) continue;
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + Mfma<T>::row(lane, v);
-        const T re = acc[t][0][v], im = acc[t][1][v];
-        if (i < a.n_samples) {
-          cplx<T> z;
-          z.re = re;
-          z.im = im;
-          wout[(size_t)i * a.ldw + j] = z;
-        }
-        const double w2 = (double)re * (double)re + (double)im * (double)im;
-        if (j < cm)
-          np0[v] += w2;
-        else
-          np1[v] += w2;
-      }
-    }
+    __syncthreads();
   }
-  // lanes with equal grp hold the same rows: reduce over the 16 columns, then over waves
+  // W rows out; per-sample partial sums over this lane's column, then over the 16 columns
+  // of the sub-tile (lanes with equal grp hold the same samples), then over the two waves
+  // of a column half
+  const int j = j0 + wc * 16 + col;
+  double np0[4], np1[4];
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + wa * 16 + Mfma<T>::row(lane, v);
+    const T re = acc[0][v], im = acc[1][v];
+    if (i < S && j < ncols) {
+      cplx<T> z;
+      z.re = re;
+      z.im = im;
+      wout[(size_t)i * a.ldw + j] = z;
+    }
+    const double w2 = j < ncols ? (double)re * (double)re + (double)im * (double)im : 0.0;
+    np0[v] = j < cm ? w2 : 0.0;
+    np1[v] = j < cm ? 0.0 : w2;
+  }
   for (int v = 0; v < 4; ++v)
     for (int o = 1; o < 16; o <<= 1) {
       np0[v] += __shfl_xor(np0[v], o);
@@ -115,30 +120,45 @@ __global__ __launch_bounds__(256) void sample_site_kernel(SampleSite a) {
     }
   if (col == 0)
     for (int v = 0; v < 4; ++v) {
-      const int r = Mfma<T>::row(lane, v);
-      part[wave][r][0] = np0[v];
-      part[wave][r][1] = np1[v];
+      const int r = wa * 16 + Mfma<T>::row(lane, v);
+      red[wc][r][0] = np0[v];
+      red[wc][r][1] = np1[v];
     }
   __syncthreads();
-  if (tid < 16) {
+  if (tid < 32) {
     const int i = i0 + tid;
-    if (i < a.n_samples) {
-      const double p0 = (part[0][tid][0] + part[1][tid][0]) + (part[2][tid][0] + part[3][tid][0]);
-      const double p1 = (part[0][tid][1] + part[1][tid][1]) + (part[2][tid][1] + part[3][tid][1]);
-      const double tot = p0 + p1;
-      const double u = a.u[(size_t)i * a.ustride];
-      int b = 0;
-      if (!(tot > 0.0) || !isfinite(tot)) {
-        atomicOr(a.err, 1);
-      } else {
-        b = (u < p0 / tot) ? 0 : 1;
-      }
-      const double pb = b ? p1 : p0;
-      a.bits[(size_t)i * a.bstride] = (uint8_t)b;
-      a.sel_out[i] = b;
-      a.scale_out[i] = pb > 0.0 ? 1.0 / sqrt(pb) : 0.0;
+    if (i < S) {
+      double* pt = a.part + ((size_t)i * a.ntiles + blockIdx.y) * 2;
+      pt[0] = red[0][tid][0] + red[1][tid][0];
+      pt[1] = red[0][tid][1] + red[1][tid][1];
     }
   }
+}
+
+// Step 2: per sample, p_0 and p_1 summed over the column tiles in order (deterministic),
+// bit q = (u_i < p_0 / (p_0 + p_1)) ? 0 : 1 in FP64, the chosen plane and 1 / sqrt(p_bit)
+// for the next site.
+__global__ __launch_bounds__(256) void sample_decide_kernel(SampleSite a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n_samples) return;
+  const double* pt = a.part + (size_t)i * a.ntiles * 2;
+  double p0 = 0.0, p1 = 0.0;
+  for (int t = 0; t < a.ntiles; ++t) {
+    p0 += pt[2 * t];
+    p1 += pt[2 * t + 1];
+  }
+  const double tot = p0 + p1;
+  const double u = a.u[(size_t)i * a.ustride];
+  int b = 0;
+  if (!(tot > 0.0) || !isfinite(tot)) {
+    atomicOr(a.err, 1);
+  } else {
+    b = (u < p0 / tot) ? 0 : 1;
+  }
+  const double pb = b ? p1 : p0;
+  a.bits[(size_t)i * a.bstride] = (uint8_t)b;
+  a.sel_out[i] = b;
+  a.scale_out[i] = pb > 0.0 ? 1.0 / sqrt(pb) : 0.0;
 }
 
 // Lambda[i] /= n for the inner bonds i = 1..N-1 and Gamma[q] *= n for the inner sites
@@ -170,8 +190,12 @@ __global__ void scale_state_kernel(void* gamma_base, size_t slot_elems, double* 
 
 template <class T>
 void launch_sample_site(const SampleSite& a, hipStream_t stream) {
-  const int blocks = (a.n_samples + 15) / 16;
-  hipLaunchKernelGGL(sample_site_kernel<T>, dim3(blocks), dim3(256), 0, stream, a);
+  // a.ntiles = ceil(2 cm / 32) column tiles; a.part holds n_samples x ntiles x 2 doubles
+  const int row_tiles = (a.n_samples + 31) / 32;
+  hipLaunchKernelGGL(sample_contract_kernel<T>, dim3(row_tiles, a.ntiles), dim3(256), 0, stream,
+                     a);
+  hipLaunchKernelGGL(sample_decide_kernel, dim3((a.n_samples + 255) / 256), dim3(256), 0, stream,
+                     a);
 }
 
 template <class T>
