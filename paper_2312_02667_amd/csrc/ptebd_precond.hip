@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void gram64_kernel(const GateDesc* __restrict_
   if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
   int ti, tj;
   tile_of(blockIdx.x, nt, ti, tj);
-  const z32* __restrict__ W = (const z32*)d->w;
+  const gptr<const z32> __restrict__ W = as_global((const z32*)d->w);
   const int* __restrict__ ps = po.ps + (size_t)g * po.cmax;
   z64* __restrict__ G = (z64*)d->gram;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -116,31 +116,37 @@ __global__ __launch_bounds__(256) void gram64_kernel(const GateDesc* __restrict_
   const int i0 = ti * 32 + (wave >> 1) * 16, j0 = tj * 32 + (wave & 1) * 16;
   const int ci = i0 + col, cj = j0 + col;
   const bool oki = ci < C, okj = cj < C;
-  const z32* __restrict__ wi = W + (size_t)(oki ? ps[ci] : 0) * R;
-  const z32* __restrict__ wj = W + (size_t)(okj ? ps[cj] : 0) * R;
+  const uint32_t offi = (uint32_t)(oki ? ps[ci] : 0) * (uint32_t)R;
+  const uint32_t offj = (uint32_t)(okj ? ps[cj] : 0) * (uint32_t)R;
   typedef Mfma<double>::v4 V4;
   V4 acc[2];
   for (int v = 0; v < 4; ++v) {
     acc[0][v] = 0.0;
     acc[1][v] = 0.0;
   }
-  for (int r0 = 0; r0 < R; r0 += 4) {
-    const int r = r0 + grp;
-    z64 x, y;
-    x.re = x.im = y.re = y.im = 0.0;
-    if (r < R) {
-      if (oki) {
-        const z32 a = wi[r];
-        x.re = a.re;
-        x.im = a.im;
-      }
-      if (okj) {
-        const z32 b = wj[r];
-        y.re = b.re;
-        y.im = b.im;
-      }
+  // 16 rows per step: the eight loads of a lane are unconditional (an out-of-range row
+  // reads row 0) and issued together, masked where used
+  for (int r0 = 0; r0 < R; r0 += 16) {
+    z32 xa[4], ya[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 4 * u + grp;
+      const uint32_t rc = r < R ? r : 0;
+      xa[u] = gload<float>(gat<float>(W, offi + rc));
+      ya[u] = gload<float>(gat<float>(W, offj + rc));
     }
-    gram_mfma<double>(acc, x, y);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool rok = r0 + 4 * u + grp < R;
+      const z32 a = cmask<float>(xa[u], oki && rok), b = cmask<float>(ya[u], okj && rok);
+      z64 x, y;
+      x.re = a.re;
+      x.im = a.im;
+      y.re = b.re;
+      y.im = b.im;
+      gram_mfma<double>(acc, x, y);
+    }
   }
   for (int v = 0; v < 4; ++v) {
     const int i = i0 + Mfma<double>::row(lane, v), j = j0 + col;
@@ -295,15 +301,27 @@ __global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ 
     acc[0][v] = 0.0;
     acc[1][v] = 0.0;
   }
-  for (int l0 = 0; l0 < nb; l0 += 4) {
-    const int l = l0 + grp;
-    z64 x, y;
-    x.re = x.im = y.re = y.im = 0.0;
-    if (l < nb) {
-      if (ci < C) x = G[(size_t)ci * C + b0 + l];
-      if (cj < C) y = G[(size_t)cj * C + b0 + l];
+  // the block row of R: 32 values per column, loaded together (out-of-range entries read
+  // entry b0 of column 0 and are masked)
+  const gptr<const z64> Gg = as_global((const z64*)G);
+  const uint32_t offi = (uint32_t)(ci < C ? ci : 0) * (uint32_t)C + b0;
+  const uint32_t offj = (uint32_t)(cj < C ? cj : 0) * (uint32_t)C + b0;
+  for (int l0 = 0; l0 < nb; l0 += 16) {
+    z64 xa[4], ya[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int l = l0 + 4 * u + grp;
+      const uint32_t lc = l < nb ? l : 0;
+      xa[u] = gload<double>(gat<double>(Gg, offi + lc));
+      ya[u] = gload<double>(gat<double>(Gg, offj + lc));
     }
-    gram_mfma<double>(acc, x, y);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool lok = l0 + 4 * u + grp < nb;
+      gram_mfma<double>(acc, cmask<double>(xa[u], ci < C && lok),
+                        cmask<double>(ya[u], cj < C && lok));
+    }
   }
   for (int v = 0; v < 4; ++v) {
     const int i = i0 + Mfma<double>::row(lane, v), j = j0 + col;
@@ -389,15 +407,25 @@ __global__ __launch_bounds__(256) void ugemm_kernel(const GateDesc* __restrict__
     acc[0][v] = 0.f;
     acc[1][v] = 0.f;
   }
-  for (int k0 = 0; k0 < C; k0 += 4) {
-    const int kk = k0 + grp;
-    z32 a, b;
-    a.re = a.im = b.re = b.im = 0.f;
-    if (kk < C) {
-      if (rr < R) a = W[(size_t)kk * R + rr];
-      if (cl >= 0) b = Y[(size_t)cl * C + kk];
+  // 16 values of K per step, the eight loads of a lane issued together (out-of-range
+  // indices read entry 0 and are masked)
+  const gptr<const z32> Wg = as_global(W), Yg = as_global(Y);
+  const uint32_t rc = rr < R ? rr : 0, yoff = (uint32_t)(cl >= 0 ? cl : 0) * (uint32_t)C;
+  for (int k0 = 0; k0 < C; k0 += 16) {
+    z32 aa[4], bb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + 4 * u + grp;
+      const uint32_t kc = kk < C ? kk : 0;
+      aa[u] = gload<float>(gat<float>(Wg, kc * (uint32_t)R + rc));
+      bb[u] = gload<float>(gat<float>(Yg, yoff + kc));
     }
-    cmfma<float>(acc, a, b);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool kok = k0 + 4 * u + grp < C;
+      cmfma<float>(acc, cmask<float>(aa[u], rr < R && kok), cmask<float>(bb[u], cl >= 0 && kok));
+    }
   }
   for (int v = 0; v < 4; ++v) {
     const int r = r0 + (wave >> 1) * 16 + Mfma<float>::row(lane, v);
