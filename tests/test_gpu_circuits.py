@@ -32,6 +32,30 @@ def test_mixed_path_against_oracle_at_chi_256(precondition):
     m.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("chi", [20, 40, 100])
+def test_mixed_path_ragged_caps(precision, chi):
+    """Caps whose theta widths (2 chi = 40, 80, 200) are not multiples of the 16-column Jacobi
+    blocks or the 32-column preconditioner tiles, and give an odd block count (13 at
+    chi = 100): N = 30, depth 12, Haar SU(4), against the FP64 oracle (err_F and bond
+    dimensions after every layer from the first truncating one)."""
+    n, depth = 30, 12
+    layers = inputs.brickwork_circuit(n, depth, seed=11)
+    ref = po.product_state(n)
+    m = ptebd.MPS(n, chi, precision)
+    bound = 1e-6 if precision == "fp32" else 1e-12
+    for li, (bonds, gates) in enumerate(layers):
+        st = m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12)
+        assert st["n_unconverged"] == 0
+        po.apply_layer(ref, bonds, gates, chi_max=chi, cutoff=oracle_cutoff(1e-12, precision))
+        if max(ref.bond_dims()) >= chi:
+            err = po.fidelity_error(ref, to_oracle(m))
+            say(f"{precision} chi={chi} layer {li + 1}: err_F {err:.3e}")
+            assert err <= bound
+            assert m.bond_dims() == ref.bond_dims()
+    m.close()
+
+
 def test_batched_states_match_separate_runs():
     """Three circuits of different N and chi_max in one handle (one launch per layer over all
     of them) give bitwise the same states as three separate handles."""
