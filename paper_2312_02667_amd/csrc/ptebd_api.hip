@@ -213,8 +213,8 @@ namespace {
 
 // Layout of the per-gate output block inside outbuf.
 struct OutLayout {
-  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, ps, gmax, work, total;
-  int nslot;
+  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, ps, gmax, work, rstart, total;
+  int nslot, nbmax;
 };
 
 // Column-block pairs per round of the block Jacobi for matrices of up to cmax columns.
@@ -245,6 +245,8 @@ OutLayout out_layout(int n, int cmax) {
   L.gmax = take(sizeof(double) * n);
   L.nslot = pair_slots(cmax);
   L.work = take(sizeof(uint32_t) * 2 * (size_t)n * L.nslot);
+  L.nbmax = (cmax + 15) / 16;
+  L.rstart = take(sizeof(int32_t) * (size_t)n * L.nbmax);
   L.total = off;
   return L;
 }
@@ -264,6 +266,9 @@ LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
   o.counters = (int32_t*)(b + L.counters);
   o.work = (uint32_t*)(b + L.work);
   o.nslot = L.nslot;
+  o.rstart = (int32_t*)(b + L.rstart);
+  o.nbmax = L.nbmax;
+  o.triangular = 0;
   o.cmax = cmax;
   return o;
 }
@@ -411,7 +416,8 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   const GateDesc* d_desc = (const GateDesc*)h->desc.p;
   const GateDesc* d_jdesc = pre ? d_desc + n : d_desc;
   const GateDesc* d_wdesc = pre ? d_desc + 2 * n : d_desc;
-  const LayerOut lo = make_layer_out(h->outbuf.p, L, cmax);
+  LayerOut lo = make_layer_out(h->outbuf.p, L, cmax);
+  lo.triangular = pre ? 1 : 0;  // the Jacobi then starts from X = R^H, lower triangular
   ptebd::PrecondOut po;
   po.ps = (int32_t*)((char*)h->outbuf.p + L.ps);
   po.gmax = (double*)((char*)h->outbuf.p + L.gmax);
@@ -464,25 +470,21 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   if (pf->on) {
     pf->harvest();
     const double ce = (double)sizeof(cplx<T>);
-    // executed Jacobi pairs per gate: Gram pairs cost 6144 R flops and 32 R complex reads,
-    // rotated pairs 8192 (R + C) flops and 64 (R + C) complex reads and writes (R + 0 when
-    // the right vectors are not accumulated)
+    // executed Jacobi rows: a Gram matrix over r rows costs 6144 r flops and 32 r complex
+    // reads, a rotation of r rows (W's, plus V's) 8192 r flops and 64 r complex reads and
+    // writes
     const size_t wn = sizeof(uint32_t) * 2 * (size_t)n * L.nslot;
     PT_HIP(hipMemcpyAsync((char*)h->h_out.p + L.work, (char*)h->outbuf.p + L.work, wn,
                           hipMemcpyDeviceToHost, stream));
     PT_HIP(hipStreamSynchronize(stream));
     const uint32_t* hw = (const uint32_t*)(ho + L.work);
-    const GateDesc* hj = (const GateDesc*)h->h_desc.p + (pre ? n : 0);
-    for (int i = 0; i < n; ++i) {
-      double pairs = 0.0, rotated = 0.0;
-      for (int x = 0; x < L.nslot; ++x) {
-        pairs += hw[2 * ((size_t)i * L.nslot + x)];
-        rotated += hw[2 * ((size_t)i * L.nslot + x) + 1];
-      }
-      const double rj = hj[i].R, rot_rows = rj + (hj[i].v != nullptr ? (double)hj[i].C : 0.0);
-      pf->st[PTEBD_KERNEL_JACOBI].flops += 6144.0 * rj * pairs + 8192.0 * rot_rows * rotated;
-      pf->st[PTEBD_KERNEL_JACOBI].bytes += ce * (32.0 * rj * pairs + 64.0 * rot_rows * rotated);
+    double gram_rows = 0.0, rot_rows = 0.0;
+    for (size_t x = 0; x < (size_t)n * L.nslot; ++x) {
+      gram_rows += hw[2 * x];
+      rot_rows += hw[2 * x + 1];
     }
+    pf->st[PTEBD_KERNEL_JACOBI].flops += 6144.0 * gram_rows + 8192.0 * rot_rows;
+    pf->st[PTEBD_KERNEL_JACOBI].bytes += ce * (32.0 * gram_rows + 64.0 * rot_rows);
     for (int i = 0; i < n; ++i) {
       const GateDesc& d = descs[i];
       const double cl = d.cl, cm = d.cm, cr = d.cr, kk = hk[i];

@@ -66,13 +66,20 @@ struct LayerOut {
   uint32_t* offbits; // max relative off-diagonal of the sweep (float bits)
   int32_t* counters; // [0..1] unconverged counts (double-buffered by sweep parity),
                      // [2] error flags: bit0 annihilated, bit1 non-finite
-  uint32_t* work;    // executed Jacobi pairs per (gate, pair slot): work[2 (g nslot + x)] counts
-                     // the pairs whose Gram matrix was formed, work[2 (g nslot + x) + 1] the
-                     // rotated ones.  One workgroup owns a slot in a launch, so these counts
-                     // never contend (a handful of shared counters for every workgroup of a
-                     // launch serialize in one L2 channel and cost a large share of the
-                     // Gram phase).
+  uint32_t* work;    // executed Jacobi rows per (gate, pair slot): work[2 (g nslot + x)] sums
+                     // the rows over which Gram matrices were formed, work[2 (g nslot + x) + 1]
+                     // the rows rotated (W's, plus V's when accumulated).  One workgroup owns a
+                     // slot in a launch, so these counts never contend (a handful of shared
+                     // counters for every workgroup of a launch serialize in one L2 channel
+                     // and cost a large share of the Gram phase).
   int32_t nslot;     // pair slots per gate: half the even block count of cmax
+  int32_t* rstart;   // per gate and 16-column block: the first row of W that can be nonzero
+                     // (n x nbmax).  A pair skips the 16-row chunks below the smaller of its
+                     // blocks' starts (exact zeros in both); a rotated pair gives both blocks
+                     // that start.
+  int32_t nbmax;     // 16-column blocks of cmax
+  int32_t triangular;  // 1: the Jacobi starts from a lower-triangular W (block b starts at
+                       // row 16 b), 0: every block starts at row 0
   int32_t cmax;
 };
 

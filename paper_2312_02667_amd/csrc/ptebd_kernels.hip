@@ -220,6 +220,8 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < 2 * out.nslot; i += blockDim.x)
       out.work[(size_t)g * 2 * out.nslot + i] = 0u;
+    for (int b = threadIdx.x; b < out.nbmax; b += blockDim.x)
+      out.rstart[(size_t)g * out.nbmax + b] = out.triangular ? 16 * b : 0;
     if (threadIdx.x == 0) {
       out.conv[g] = 0;
       out.sweeps[g] = 0;
@@ -271,6 +273,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   if ((dummy_i || dummy_j) && nb > 1) return;
   const int cI = dummy_i ? 0 : I * 16, cJ = dummy_j ? 0 : J * 16;
   const int nI = dummy_i ? 0 : min(16, C - cI), nJ = dummy_j ? 0 : min(16, C - cJ);
+  // Rows below both blocks' first possibly nonzero row are exact zeros in all 32 columns
+  // (on the mixed path W starts lower triangular): every wave skips its 16-row chunks there,
+  // keeping the chunk-to-wave assignment (and so every sum) as without the skip.
+  int32_t* __restrict__ rsg = out.rstart + (size_t)g * out.nbmax;
+  const int rs0 = min(dummy_i ? R : rsg[I], dummy_j ? R : rsg[J]);
+  const int c0 = rs0 >> 4;  // first chunk that can hold a nonzero row
   const gptr<cplx<T>> __restrict__ W = as_global((cplx<T>*)d->w);
   const gptr<cplx<T>> __restrict__ V = as_global((cplx<T>*)d->v);
 
@@ -286,6 +294,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: scalar loop bounds
+  const int wstart = 16 * (c0 + (((wave - c0) % 4) + 4) % 4);  // this wave's first chunk
   const int col = lane & 15, grp = lane >> 4;
   typedef typename Mfma<T>::v4 V4;
 
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
     };
     // The prefetch is unconditional (a wave's last chunk re-reads itself, from cache): a
     // load under a branch would make the compiler wait for it before this chunk's products.
-    int r0 = wave * 16;
+    int r0 = wstart;
     if (r0 < R) load_chunk(r0, xi, xj);
     for (; r0 < R; r0 += 64) {
       load_chunk(r0 + 64 < R ? r0 + 64 : r0, ni, nj);
@@ -427,8 +436,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   if (tid == 0) {
     atomicMax(&out.offbits[g], __float_as_uint((float)mx));
     uint32_t* wk = out.work + ((size_t)g * out.nslot + blockIdx.x) * 2;  // this pair's slot
-    atomicAdd(wk, 1u);
-    if (rotate) atomicAdd(wk + 1, 1u);
+    const uint32_t rows = (uint32_t)(R - 16 * c0 > 0 ? R - 16 * c0 : 0);
+    atomicAdd(wk, rows);
+    if (rotate) {
+      atomicAdd(wk + 1, rows + (V != nullptr ? (uint32_t)C : 0u));
+      // both blocks' columns are now combinations of the two: nonzero from rs0 on
+      if (!dummy_i) rsg[I] = rs0;
+      if (!dummy_j) rsg[J] = rs0;
+    }
   }
   if (!rotate) return;  // uniform: every thread read the same red[]
 
@@ -581,7 +596,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) dst[ks] = gload<T>(gat<T>(M, coff[ks] + rr));
     };
-    int rb = wave * 16;
+    int rb = pass == 0 ? wstart : wave * 16;  // V (pass 1) is not triangular
     if (rb < rows) load_rows(rb, av);
     for (; rb < rows; rb += 64) {
       load_rows(rb + 64 < rows ? rb + 64 : rb, an);  // unconditional, as in the Gram loop
