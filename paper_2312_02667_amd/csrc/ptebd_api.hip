@@ -119,6 +119,7 @@ struct Prof {
   struct Pend {
     int kind;
     hipEvent_t a, b;
+    int count;  // launches the interval stands for
   };
   std::vector<hipEvent_t> pool;
   std::vector<Pend> pending;
@@ -143,7 +144,7 @@ struct Prof {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         st[p.kind].total_ms += ms;
-        st[p.kind].launches += 1;
+        st[p.kind].launches += p.count;
       }
       pool.push_back(p.a);
       pool.push_back(p.b);
@@ -172,7 +173,7 @@ void timed(Prof* pf, int kind, hipStream_t stream, F fn) {
   (void)hipEventRecord(a, stream);
   fn();
   (void)hipEventRecord(b, stream);
-  pf->pending.push_back({kind, a, b});
+  pf->pending.push_back({kind, a, b, 1});
 }
 
 double unit_roundoff(int precision) {
@@ -197,7 +198,11 @@ struct ptebd_mps {
   double inner_repeat = 0.0;
   int sort_pairs = 1;
   int precondition = 1;  // FP32 handles only
+  int streams = 2;       // Jacobi sweeps of a large batch on two streams
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // second stream of the Jacobi sweeps and its fork / join events, created on first use
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   char* gamma_slot(int s, int q) const {
     const StateInfo& si = st[s];
@@ -213,7 +218,8 @@ namespace {
 
 // Layout of the per-gate output block inside outbuf.
 struct OutLayout {
-  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, ps, gmax, work, rstart, total;
+  size_t sig, perm, k, r, eps, nu, sweeps, conv, offbits, counters, ps, gmax, work, rstart,
+      counters2, total;
   int nslot, nbmax;
 };
 
@@ -247,6 +253,7 @@ OutLayout out_layout(int n, int cmax) {
   L.work = take(sizeof(uint32_t) * 2 * (size_t)n * L.nslot);
   L.nbmax = (cmax + 15) / 16;
   L.rstart = take(sizeof(int32_t) * (size_t)n * L.nbmax);
+  L.counters2 = take(sizeof(int32_t) * 4);  // the second half's sweep counters
   L.total = off;
   return L;
 }
@@ -273,35 +280,138 @@ LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
   return o;
 }
 
-// Sweeps of the block Jacobi SVD on descriptors already on the device.
+// The per-gate outputs of gates off.. of a layer (their own sweep counters).
+LayerOut shift_out(const LayerOut& o, int off, int32_t* counters) {
+  LayerOut r = o;
+  r.sig += (size_t)off * o.cmax;
+  r.perm += (size_t)off * o.cmax;
+  r.k += off;
+  r.r += off;
+  r.eps += off;
+  r.nu += off;
+  r.sweeps += off;
+  r.conv += off;
+  r.offbits += off;
+  r.counters = counters;
+  r.work += (size_t)off * 2 * o.nslot;
+  r.rstart += (size_t)off * o.nbmax;
+  return r;
+}
+
+// A second stream for the Jacobi sweeps: one half of the gates runs on it.
+struct SplitStreams {
+  hipStream_t s2;
+  hipEvent_t ev_fork, ev_join;
+  int32_t* counters2;  // device, 4 ints
+};
+
+// Sweeps of the block Jacobi SVD on descriptors already on the device.  With `split`, gates
+// [0, n/2) run on `stream` and [n/2, n) on split->s2: each half launches its own rounds and
+// convergence check, so one half's launches fill the GPU while the other's drain; the host
+// reads both halves' counters after every sweep.  When profiling, a sweep's rounds are
+// timed as one interval spanning both streams (each round counts as one launch over all
+// gates), since the durations of overlapping launches would not describe the kernel.
 template <class T>
 int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, const LayerOut& lo,
                int precision, int max_sweeps, double tol_factor, int inner_sweeps,
                double inner_repeat, int sort_pairs, int32_t* h_counter, int* n_unconverged,
-               Prof* pf) {
-  ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
+               Prof* pf, const SplitStreams* split = nullptr) {
   int nb = (max_c + 15) / 16;
   int nbp = nb + (nb & 1);
   if (nbp < 2) nbp = 2;
   const double u = unit_roundoff(precision);
-  int remaining = n;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int round = 0; round < nbp - 1; ++round)
-      timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
-        ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
-                                      inner_repeat, sort_pairs, stream);
-      });
-    ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
-    PT_HIP(hipGetLastError());
-    PT_HIP(hipMemcpyAsync(h_counter, lo.counters + (sweep & 1), sizeof(int32_t),
-                          hipMemcpyDeviceToHost, stream));
-    PT_HIP(hipStreamSynchronize(stream));
-    if (pf) pf->harvest();
-    remaining = *h_counter;
-    if (remaining == 0) break;
+  if (!split) {
+    ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
+    int remaining = n;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      for (int round = 0; round < nbp - 1; ++round)
+        timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
+          ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
+                                        inner_repeat, sort_pairs, stream);
+        });
+      ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
+      PT_HIP(hipGetLastError());
+      PT_HIP(hipMemcpyAsync(h_counter, lo.counters + (sweep & 1), sizeof(int32_t),
+                            hipMemcpyDeviceToHost, stream));
+      PT_HIP(hipStreamSynchronize(stream));
+      if (pf) pf->harvest();
+      remaining = *h_counter;
+      if (remaining == 0) break;
+    }
+    *n_unconverged = remaining;
+    return PTEBD_OK;
   }
-  *n_unconverged = remaining;
+  const int n1 = n / 2, n2 = n - n1;
+  hipStream_t st[2] = {stream, split->s2};
+  const GateDesc* dd[2] = {d_desc, d_desc + n1};
+  const int nn[2] = {n1, n2};
+  const LayerOut oo[2] = {lo, shift_out(lo, n1, split->counters2)};
+  // the second stream starts after everything already queued on the first
+  PT_HIP(hipEventRecord(split->ev_fork, stream));
+  PT_HIP(hipStreamWaitEvent(split->s2, split->ev_fork, 0));
+  for (int k = 0; k < 2; ++k) ptebd::launch_jacobi_init<T>(dd[k], nn[k], max_c, oo[k], st[k]);
+  int rem[2] = {n1, n2};
+  const bool prof = pf && pf->on;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    hipEvent_t ta = nullptr, tb = nullptr;
+    if (prof) {
+      ta = pf->get();
+      tb = pf->get();
+      if (!ta || !tb) {  // untimed sweep
+        if (ta) pf->pool.push_back(ta);
+        if (tb) pf->pool.push_back(tb);
+        ta = tb = nullptr;
+      }
+    }
+    if (ta && tb) {  // interval start, before either half's rounds
+      PT_HIP(hipEventRecord(ta, stream));
+      PT_HIP(hipStreamWaitEvent(split->s2, ta, 0));
+    }
+    for (int round = 0; round < nbp - 1; ++round)
+      for (int k = 0; k < 2; ++k)
+        if (rem[k] > 0)
+          ptebd::launch_jacobi_round<T>(dd[k], nn[k], round, nbp, oo[k], tol_factor * u,
+                                        inner_sweeps, inner_repeat, sort_pairs, st[k]);
+    if (ta && tb) {  // interval end, after both halves' rounds
+      PT_HIP(hipEventRecord(split->ev_join, split->s2));
+      PT_HIP(hipStreamWaitEvent(stream, split->ev_join, 0));
+      PT_HIP(hipEventRecord(tb, stream));
+      pf->pending.push_back({PTEBD_KERNEL_JACOBI, ta, tb, nbp - 1});
+    }
+    for (int k = 0; k < 2; ++k)
+      if (rem[k] > 0) {
+        ptebd::launch_sweep_check(dd[k], nn[k], sweep, tol_factor, u, oo[k], st[k]);
+        PT_HIP(hipMemcpyAsync(h_counter + k, oo[k].counters + (sweep & 1), sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st[k]));
+      }
+    PT_HIP(hipGetLastError());
+    for (int k = 0; k < 2; ++k) PT_HIP(hipStreamSynchronize(st[k]));
+    if (pf) pf->harvest();
+    for (int k = 0; k < 2; ++k)
+      if (rem[k] > 0) rem[k] = h_counter[k];
+    if (rem[0] == 0 && rem[1] == 0) break;
+  }
+  // later work on the first stream follows the second stream's
+  PT_HIP(hipEventRecord(split->ev_join, split->s2));
+  PT_HIP(hipStreamWaitEvent(stream, split->ev_join, 0));
+  *n_unconverged = rem[0] + rem[1];
   return PTEBD_OK;
+}
+
+// The handle's split-stream resources when its batch qualifies (nullptr: one stream).
+const SplitStreams* split_for(ptebd_mps* h, int n, const OutLayout& L, SplitStreams* out) {
+  if (h->streams < 2 || n < 64) return nullptr;
+  if (!h->stream2) {
+    if (hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess)
+      return nullptr;  // fall back to one stream
+  }
+  out->s2 = h->stream2;
+  out->ev_fork = h->ev_fork;
+  out->ev_join = h->ev_join;
+  out->counters2 = (int32_t*)((char*)h->outbuf.p + L.counters2);
+  return out;
 }
 
 // One batch of independent bond updates (all gates of a layer, or one PtSU half-step).
@@ -435,10 +545,11 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
     });
   PT_HIP(hipGetLastError());
   int n_unconv = 0;
+  SplitStreams sp;
+  const SplitStreams* split = split_for(h, n, L, &sp);
   PT_CHECK(run_jacobi<T>(stream, d_jdesc, n, max_c, lo, h->precision, h->max_sweeps,
                          h->tol_factor, h->inner_sweeps, h->inner_repeat, h->sort_pairs,
-                         (int32_t*)h->h_small.p,
-                         &n_unconv, pf));
+                         (int32_t*)h->h_small.p, &n_unconv, pf, split));
   timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_jdesc, n, cutoff, lo, stream); });
   if (pre)
     timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
@@ -698,6 +809,12 @@ int ptebd_mps_destroy(ptebd_mps_t h) {
   h->prof.release();
   if (h->ev0) (void)hipEventDestroy(h->ev0);
   if (h->ev1) (void)hipEventDestroy(h->ev1);
+  if (h->stream2) {
+    (void)hipStreamSynchronize(h->stream2);
+    (void)hipStreamDestroy(h->stream2);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   delete h;
   return PTEBD_OK;
 }
@@ -711,6 +828,7 @@ int ptebd_get_svd_params(ptebd_mps_t h, ptebd_svd_params* out) {
   out->inner_repeat = h->inner_repeat;
   out->sort_pairs = h->sort_pairs;
   out->precondition = h->precondition;
+  out->streams = h->streams;
   return PTEBD_OK;
 }
 
@@ -720,15 +838,17 @@ int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* p) {
   if (p->max_sweeps < 1 || !(p->tol_factor > 0.0) || !std::isfinite(p->tol_factor) ||
       p->inner_sweeps < 1 || p->inner_sweeps > 64 || !(p->inner_repeat >= 0.0) ||
       !std::isfinite(p->inner_repeat) || (p->sort_pairs != 0 && p->sort_pairs != 1) ||
-      (p->precondition != 0 && p->precondition != 1))
+      (p->precondition != 0 && p->precondition != 1) || (p->streams != 1 && p->streams != 2))
     return fail(PTEBD_EINVAL, "need max_sweeps >= 1, tol_factor > 0, inner_sweeps in [1, 64], "
-                              "finite inner_repeat >= 0, sort_pairs and precondition 0/1");
+                              "finite inner_repeat >= 0, sort_pairs and precondition 0/1, "
+                              "streams 1 or 2");
   h->max_sweeps = p->max_sweeps;
   h->tol_factor = p->tol_factor;
   h->inner_sweeps = p->inner_sweeps;
   h->inner_repeat = p->inner_repeat;
   h->sort_pairs = p->sort_pairs;
   h->precondition = p->precondition;
+  h->streams = p->streams;
   return PTEBD_OK;
 }
 

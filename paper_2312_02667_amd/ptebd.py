@@ -50,7 +50,8 @@ class LayerStats(ctypes.Structure):
 class SvdParams(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int), ("tol_factor", ctypes.c_double),
                 ("inner_sweeps", ctypes.c_int), ("inner_repeat", ctypes.c_double),
-                ("sort_pairs", ctypes.c_int), ("precondition", ctypes.c_int)]
+                ("sort_pairs", ctypes.c_int), ("precondition", ctypes.c_int),
+                ("streams", ctypes.c_int)]
 
 
 class KernelStats(ctypes.Structure):

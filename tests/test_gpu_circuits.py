@@ -56,6 +56,29 @@ def test_mixed_path_ragged_caps(precision, chi):
     m.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_two_streams_bit_identical(precision):
+    """A layer of >= 64 bond updates runs its Jacobi sweeps on two streams (half the gates
+    each) by default; one stream must give bitwise the same state."""
+    n, depth, chi = 200, 9, 32
+    layers = inputs.brickwork_circuit(n, depth, seed=21)
+    a = ptebd.MPS(n, chi, precision)
+    b = ptebd.MPS(n, chi, precision)
+    assert a.svd_params()["streams"] == 2
+    b.set_svd_params(streams=1)
+    for bonds, gates in layers:
+        sa = a.apply_layer(bonds, gates, chi_max=chi)
+        sb = b.apply_layer(bonds, gates, chi_max=chi)
+        assert len(bonds) >= 64
+        assert np.array_equal(sa["sweeps"], sb["sweeps"])
+    ga, la = a.export()
+    gb, lb = b.export()
+    assert all(np.array_equal(x, y) for x, y in zip(la, lb))
+    assert all(np.array_equal(x, y) for x, y in zip(ga, gb))
+    a.close()
+    b.close()
+
+
 def test_batched_states_match_separate_runs():
     """Three circuits of different N and chi_max in one handle (one launch per layer over all
     of them) give bitwise the same states as three separate handles."""
