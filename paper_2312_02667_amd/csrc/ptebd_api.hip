@@ -138,6 +138,42 @@ struct Prof {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
   }
+  // Intervals of Jacobi rounds running on two streams at once, on a common clock (events
+  // relative to `ref`): their union is the time the rounds occupied the GPU.
+  hipEvent_t ref = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> spans;
+  double span_rounds = 0.0;  // rounds over all gates the spans stand for
+  void harvest_spans(int kind) {
+    std::vector<std::pair<float, float>> iv;
+    for (const auto& sp : spans) {
+      float a = 0.f, b = 0.f;
+      if (ref && hipEventElapsedTime(&a, ref, sp.first) == hipSuccess &&
+          hipEventElapsedTime(&b, ref, sp.second) == hipSuccess)
+        iv.push_back({a, b});
+      pool.push_back(sp.first);
+      pool.push_back(sp.second);
+    }
+    std::sort(iv.begin(), iv.end());
+    double total = 0.0, lo = 0.0, hi = -1.0;
+    for (const auto& x : iv) {
+      if (x.first > hi) {
+        if (hi > lo) total += hi - lo;
+        lo = x.first;
+        hi = x.second;
+      } else if (x.second > hi) {
+        hi = x.second;
+      }
+    }
+    if (hi > lo) total += hi - lo;
+    if (!spans.empty()) {
+      st[kind].total_ms += total;
+      st[kind].launches += (int64_t)std::llround(span_rounds);
+    }
+    if (ref) pool.push_back(ref);
+    ref = nullptr;
+    spans.clear();
+    span_rounds = 0.0;
+  }
   // Harvest finished launches (the stream has been synchronized).
   void harvest() {
     for (const Pend& p : pending) {
@@ -298,103 +334,41 @@ LayerOut shift_out(const LayerOut& o, int off, int32_t* counters) {
   return r;
 }
 
-// A second stream for the Jacobi sweeps: one half of the gates runs on it.
+// A second stream: one half of a large batch runs its whole pipeline on it.
 struct SplitStreams {
   hipStream_t s2;
   hipEvent_t ev_fork, ev_join;
   int32_t* counters2;  // device, 4 ints
 };
 
-// Sweeps of the block Jacobi SVD on descriptors already on the device.  With `split`, gates
-// [0, n/2) run on `stream` and [n/2, n) on split->s2: each half launches its own rounds and
-// convergence check, so one half's launches fill the GPU while the other's drain; the host
-// reads both halves' counters after every sweep.  When profiling, a sweep's rounds are
-// timed as one interval spanning both streams (each round counts as one launch over all
-// gates), since the durations of overlapping launches would not describe the kernel.
+// Sweeps of the block Jacobi SVD on descriptors already on the device, on one stream.
 template <class T>
 int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, const LayerOut& lo,
                int precision, int max_sweeps, double tol_factor, int inner_sweeps,
                double inner_repeat, int sort_pairs, int32_t* h_counter, int* n_unconverged,
-               Prof* pf, const SplitStreams* split = nullptr) {
+               Prof* pf) {
+  ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
   int nb = (max_c + 15) / 16;
   int nbp = nb + (nb & 1);
   if (nbp < 2) nbp = 2;
   const double u = unit_roundoff(precision);
-  if (!split) {
-    ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
-    int remaining = n;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-      for (int round = 0; round < nbp - 1; ++round)
-        timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
-          ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
-                                        inner_repeat, sort_pairs, stream);
-        });
-      ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
-      PT_HIP(hipGetLastError());
-      PT_HIP(hipMemcpyAsync(h_counter, lo.counters + (sweep & 1), sizeof(int32_t),
-                            hipMemcpyDeviceToHost, stream));
-      PT_HIP(hipStreamSynchronize(stream));
-      if (pf) pf->harvest();
-      remaining = *h_counter;
-      if (remaining == 0) break;
-    }
-    *n_unconverged = remaining;
-    return PTEBD_OK;
-  }
-  const int n1 = n / 2, n2 = n - n1;
-  hipStream_t st[2] = {stream, split->s2};
-  const GateDesc* dd[2] = {d_desc, d_desc + n1};
-  const int nn[2] = {n1, n2};
-  const LayerOut oo[2] = {lo, shift_out(lo, n1, split->counters2)};
-  // the second stream starts after everything already queued on the first
-  PT_HIP(hipEventRecord(split->ev_fork, stream));
-  PT_HIP(hipStreamWaitEvent(split->s2, split->ev_fork, 0));
-  for (int k = 0; k < 2; ++k) ptebd::launch_jacobi_init<T>(dd[k], nn[k], max_c, oo[k], st[k]);
-  int rem[2] = {n1, n2};
-  const bool prof = pf && pf->on;
+  int remaining = n;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    hipEvent_t ta = nullptr, tb = nullptr;
-    if (prof) {
-      ta = pf->get();
-      tb = pf->get();
-      if (!ta || !tb) {  // untimed sweep
-        if (ta) pf->pool.push_back(ta);
-        if (tb) pf->pool.push_back(tb);
-        ta = tb = nullptr;
-      }
-    }
-    if (ta && tb) {  // interval start, before either half's rounds
-      PT_HIP(hipEventRecord(ta, stream));
-      PT_HIP(hipStreamWaitEvent(split->s2, ta, 0));
-    }
     for (int round = 0; round < nbp - 1; ++round)
-      for (int k = 0; k < 2; ++k)
-        if (rem[k] > 0)
-          ptebd::launch_jacobi_round<T>(dd[k], nn[k], round, nbp, oo[k], tol_factor * u,
-                                        inner_sweeps, inner_repeat, sort_pairs, st[k]);
-    if (ta && tb) {  // interval end, after both halves' rounds
-      PT_HIP(hipEventRecord(split->ev_join, split->s2));
-      PT_HIP(hipStreamWaitEvent(stream, split->ev_join, 0));
-      PT_HIP(hipEventRecord(tb, stream));
-      pf->pending.push_back({PTEBD_KERNEL_JACOBI, ta, tb, nbp - 1});
-    }
-    for (int k = 0; k < 2; ++k)
-      if (rem[k] > 0) {
-        ptebd::launch_sweep_check(dd[k], nn[k], sweep, tol_factor, u, oo[k], st[k]);
-        PT_HIP(hipMemcpyAsync(h_counter + k, oo[k].counters + (sweep & 1), sizeof(int32_t),
-                              hipMemcpyDeviceToHost, st[k]));
-      }
+      timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
+        ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
+                                      inner_repeat, sort_pairs, stream);
+      });
+    ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
     PT_HIP(hipGetLastError());
-    for (int k = 0; k < 2; ++k) PT_HIP(hipStreamSynchronize(st[k]));
+    PT_HIP(hipMemcpyAsync(h_counter, lo.counters + (sweep & 1), sizeof(int32_t),
+                          hipMemcpyDeviceToHost, stream));
+    PT_HIP(hipStreamSynchronize(stream));
     if (pf) pf->harvest();
-    for (int k = 0; k < 2; ++k)
-      if (rem[k] > 0) rem[k] = h_counter[k];
-    if (rem[0] == 0 && rem[1] == 0) break;
+    remaining = *h_counter;
+    if (remaining == 0) break;
   }
-  // later work on the first stream follows the second stream's
-  PT_HIP(hipEventRecord(split->ev_join, split->s2));
-  PT_HIP(hipStreamWaitEvent(stream, split->ev_join, 0));
-  *n_unconverged = rem[0] + rem[1];
+  *n_unconverged = remaining;
   return PTEBD_OK;
 }
 
@@ -412,6 +386,115 @@ const SplitStreams* split_for(ptebd_mps* h, int n, const OutLayout& L, SplitStre
   out->ev_join = h->ev_join;
   out->counters2 = (int32_t*)((char*)h->outbuf.p + L.counters2);
   return out;
+}
+
+// A large batch as two independent pipelines: gates [0, n/2) on `stream`, [n/2, n) on the
+// second stream, each running theta, the preconditioning, its own Jacobi sweeps, finalize,
+// the recovery and the write-back.  The host advances each half's sweeps as soon as its
+// own convergence counter is read, so one half's theta and preconditioning, sweep
+// boundaries and last launches overlap the other half's rounds.  Jacobi time is the union
+// of the intervals in which either half's rounds ran (events on one clock), each round over
+// half the gates counting as half a launch.  Both streams have drained on return.
+template <class T>
+int run_split(ptebd_mps* h, const SplitStreams& sp, const GateDesc* d_desc,
+              const GateDesc* d_jdesc, const GateDesc* d_wdesc, int n, int max_c, int max_r,
+              int max_tiles, bool pre, double cutoff, const LayerOut& lo,
+              const ptebd::PrecondOut& po, int32_t* h_counter, int* n_unconverged) {
+  hipStream_t stream = h->stream;
+  Prof* pf = &h->prof;
+  const bool prof = pf->on;
+  const int n1 = n / 2;
+  const int nn[2] = {n1, n - n1};
+  const int off[2] = {0, n1};
+  hipStream_t st[2] = {stream, sp.s2};
+  const LayerOut oo[2] = {lo, shift_out(lo, n1, sp.counters2)};
+  ptebd::PrecondOut pp[2] = {po, po};
+  pp[1].ps += (size_t)n1 * po.cmax;
+  pp[1].gmax += n1;
+  int nb = (max_c + 15) / 16;
+  int nbp = nb + (nb & 1);
+  if (nbp < 2) nbp = 2;
+  const double u = unit_roundoff(h->precision);
+  if (prof) {
+    pf->ref = pf->get();
+    if (pf->ref) PT_HIP(hipEventRecord(pf->ref, stream));
+  }
+  // the second stream starts after everything already queued on the first
+  PT_HIP(hipEventRecord(sp.ev_fork, stream));
+  PT_HIP(hipStreamWaitEvent(sp.s2, sp.ev_fork, 0));
+  auto front = [&](int k) {
+    const GateDesc* dd = d_desc + off[k];
+    timed(pf, PTEBD_KERNEL_THETA, st[k], [&] { ptebd::launch_theta<T>(dd, nn[k], max_tiles, st[k]); });
+    if (pre)
+      timed(pf, PTEBD_KERNEL_PRECOND, st[k], [&] {
+        ptebd::launch_colsort(dd, nn[k], pp[k], st[k]);
+        ptebd::launch_gram64(dd, nn[k], max_c, pp[k], st[k]);
+        ptebd::launch_cholesky(dd, nn[k], max_c, pp[k], st[k]);
+        ptebd::launch_xinit(d_jdesc + off[k], nn[k], max_c, st[k]);
+      });
+    ptebd::launch_jacobi_init<T>(d_jdesc + off[k], nn[k], max_c, oo[k], st[k]);
+  };
+  auto sweep = [&](int k, int sw) {
+    const GateDesc* jd = d_jdesc + off[k];
+    hipEvent_t a = prof && pf->ref ? pf->get() : nullptr;
+    hipEvent_t b = a ? pf->get() : nullptr;
+    if (a && b) PT_HIP(hipEventRecord(a, st[k]));
+    for (int round = 0; round < nbp - 1; ++round)
+      ptebd::launch_jacobi_round<T>(jd, nn[k], round, nbp, oo[k], h->tol_factor * u,
+                                    h->inner_sweeps, h->inner_repeat, h->sort_pairs, st[k]);
+    if (a && b) {
+      PT_HIP(hipEventRecord(b, st[k]));
+      pf->spans.push_back({a, b});
+      pf->span_rounds += 0.5 * (nbp - 1);
+    } else {
+      if (a) pf->pool.push_back(a);
+      if (b) pf->pool.push_back(b);
+    }
+    ptebd::launch_sweep_check(jd, nn[k], sw, h->tol_factor, u, oo[k], st[k]);
+    PT_HIP(hipMemcpyAsync(h_counter + k, oo[k].counters + (sw & 1), sizeof(int32_t),
+                          hipMemcpyDeviceToHost, st[k]));
+    return PTEBD_OK;
+  };
+  auto back = [&](int k) {
+    const GateDesc* jd = d_jdesc + off[k];
+    timed(pf, PTEBD_KERNEL_FINALIZE, st[k], [&] { ptebd::launch_finalize<T>(jd, nn[k], cutoff, oo[k], st[k]); });
+    if (pre)
+      timed(pf, PTEBD_KERNEL_PRECOND, st[k], [&] {
+        ptebd::launch_recover(d_desc + off[k], jd, nn[k], max_r, max_c, pp[k], oo[k], st[k]);
+      });
+    timed(pf, PTEBD_KERNEL_WRITEBACK, st[k], [&] { ptebd::launch_writeback<T>(d_wdesc + off[k], nn[k], oo[k], st[k]); });
+  };
+  int sw[2] = {0, 0};
+  bool active[2] = {true, true};
+  for (int k = 0; k < 2; ++k) {
+    front(k);
+    PT_CHECK(sweep(k, 0));
+  }
+  PT_HIP(hipGetLastError());
+  int unconv = 0;
+  while (active[0] || active[1]) {
+    for (int k = 0; k < 2; ++k) {
+      if (!active[k]) continue;
+      PT_HIP(hipStreamSynchronize(st[k]));
+      const int rem = h_counter[k];
+      ++sw[k];
+      if (rem == 0 || sw[k] >= h->max_sweeps) {
+        active[k] = false;
+        unconv += rem;
+        back(k);
+      } else {
+        PT_CHECK(sweep(k, sw[k]));
+      }
+      PT_HIP(hipGetLastError());
+    }
+  }
+  for (int k = 0; k < 2; ++k) PT_HIP(hipStreamSynchronize(st[k]));
+  if (prof) {
+    pf->harvest();
+    pf->harvest_spans(PTEBD_KERNEL_JACOBI);
+  }
+  *n_unconverged = unconv;
+  return PTEBD_OK;
 }
 
 // One batch of independent bond updates (all gates of a layer, or one PtSU half-step).
@@ -534,29 +617,34 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   po.cmax = cmax;
 
   Prof* pf = &h->prof;
-  timed(pf, PTEBD_KERNEL_THETA, stream, [&] { ptebd::launch_theta<T>(d_desc, n, max_tiles, stream); });
-  PT_HIP(hipGetLastError());
-  if (pre)
-    timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
-      ptebd::launch_colsort(d_desc, n, po, stream);
-      ptebd::launch_gram64(d_desc, n, max_c, po, stream);
-      ptebd::launch_cholesky(d_desc, n, max_c, po, stream);
-      ptebd::launch_xinit(d_jdesc, n, max_c, stream);
-    });
-  PT_HIP(hipGetLastError());
   int n_unconv = 0;
   SplitStreams sp;
   const SplitStreams* split = split_for(h, n, L, &sp);
-  PT_CHECK(run_jacobi<T>(stream, d_jdesc, n, max_c, lo, h->precision, h->max_sweeps,
-                         h->tol_factor, h->inner_sweeps, h->inner_repeat, h->sort_pairs,
-                         (int32_t*)h->h_small.p, &n_unconv, pf, split));
-  timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_jdesc, n, cutoff, lo, stream); });
-  if (pre)
-    timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
-      ptebd::launch_recover(d_desc, d_jdesc, n, max_r, max_c, po, lo, stream);
-    });
-  timed(pf, PTEBD_KERNEL_WRITEBACK, stream, [&] { ptebd::launch_writeback<T>(d_wdesc, n, lo, stream); });
-  PT_HIP(hipGetLastError());
+  if (split) {
+    PT_CHECK(run_split<T>(h, *split, d_desc, d_jdesc, d_wdesc, n, max_c, max_r, max_tiles, pre,
+                          cutoff, lo, po, (int32_t*)h->h_small.p, &n_unconv));
+  } else {
+    timed(pf, PTEBD_KERNEL_THETA, stream, [&] { ptebd::launch_theta<T>(d_desc, n, max_tiles, stream); });
+    PT_HIP(hipGetLastError());
+    if (pre)
+      timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
+        ptebd::launch_colsort(d_desc, n, po, stream);
+        ptebd::launch_gram64(d_desc, n, max_c, po, stream);
+        ptebd::launch_cholesky(d_desc, n, max_c, po, stream);
+        ptebd::launch_xinit(d_jdesc, n, max_c, stream);
+      });
+    PT_HIP(hipGetLastError());
+    PT_CHECK(run_jacobi<T>(stream, d_jdesc, n, max_c, lo, h->precision, h->max_sweeps,
+                           h->tol_factor, h->inner_sweeps, h->inner_repeat, h->sort_pairs,
+                           (int32_t*)h->h_small.p, &n_unconv, pf));
+    timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_jdesc, n, cutoff, lo, stream); });
+    if (pre)
+      timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
+        ptebd::launch_recover(d_desc, d_jdesc, n, max_r, max_c, po, lo, stream);
+      });
+    timed(pf, PTEBD_KERNEL_WRITEBACK, stream, [&] { ptebd::launch_writeback<T>(d_wdesc, n, lo, stream); });
+    PT_HIP(hipGetLastError());
+  }
   // copy back the small per-gate outputs (k .. counters are contiguous after perm)
   PT_HIP(hipMemcpyAsync((char*)h->h_out.p + L.k, (char*)h->outbuf.p + L.k, L.ps - L.k,
                         hipMemcpyDeviceToHost, stream));
@@ -567,7 +655,13 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   const double* he = (const double*)(ho + L.eps);
   const double* hn = (const double*)(ho + L.nu);
   const int32_t* hs = (const int32_t*)(ho + L.sweeps);
-  const int32_t* hc = (const int32_t*)(ho + L.counters);
+  int32_t hc[4];
+  std::memcpy(hc, ho + L.counters, sizeof(hc));
+  if (split) {  // the second half's finalize flags its errors in its own counters
+    int32_t c2[4];
+    PT_HIP(hipMemcpy(c2, (char*)h->outbuf.p + L.counters2, sizeof(c2), hipMemcpyDeviceToHost));
+    hc[2] |= c2[2];
+  }
   for (int i = 0; i < n; ++i) {
     res->k[i] = hk[i];
     res->r[i] = hr[i];
