@@ -246,8 +246,9 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
 // LDS: G and Q (2 x 32 x 33 complex T), both rotated in place; the cross-wave reduction of
 // the Gram tiles and the permuted copy of Q used by the column update alias them.
 //
-// Occupancy: the kernel is bound by the latency of its phases, so it is built for five waves
-// per SIMD in FP32 (at most 96 registers, no spills) and three in FP64 (at most 168).
+// Occupancy: the kernel is bound by the latency of its phases, so it is built for at least
+// five waves per SIMD in FP32 (at most 96 registers, no spills) and three in FP64 (at most
+// 168).
 template <class T>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
                                                            int round, int nbp, LayerOut out,
