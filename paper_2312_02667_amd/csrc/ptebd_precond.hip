@@ -229,7 +229,10 @@ __global__ __launch_bounds__(256) void potrf_kernel(const GateDesc* __restrict__
 }
 
 // Block row: X = R_kk^{-H} G[kb, j] for the tiles j > kb (blockIdx.x + kb + 1), forward
-// substitution with the lower-triangular R_kk^H; one thread per column of the tile.
+// substitution with the lower-triangular R_kk^H.  Column j of the tile is solved by the 8
+// lanes 8j .. 8j + 7 of one wave: lane s sums the terms l = s mod 8 of each row and keeps the
+// solved rows l = s mod 8 in registers; shuffles complete the sum in all 8 lanes, which then
+// scale by the reciprocal pivot (zero for a dropped pivot).
 __global__ __launch_bounds__(256) void trsm_kernel(const GateDesc* __restrict__ descs,
                                                    int kb) {
   const int g = blockIdx.y;
@@ -241,6 +244,7 @@ __global__ __launch_bounds__(256) void trsm_kernel(const GateDesc* __restrict__ 
   z64* __restrict__ G = (z64*)descs[g].gram;
   __shared__ z64 Rk[32][33];
   __shared__ z64 X[32][33];
+  __shared__ double rinv[32];
   const int tid = threadIdx.x;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e & 31, j = e >> 5;
@@ -254,29 +258,65 @@ __global__ __launch_bounds__(256) void trsm_kernel(const GateDesc* __restrict__ 
     X[i][j] = x;
   }
   __syncthreads();
-  if (tid < 32 && tid < nc) {
-    const int j = tid;
-    for (int i = 0; i < nb; ++i) {
-      // X[i][j] = (X[i][j] - sum_{l<i} conj(Rk[l][i]) X[l][j]) / Rk[i][i]
-      double re = X[i][j].re, im = X[i][j].im;
-      for (int l = 0; l < i; ++l) {
-        const z64 r = Rk[l][i], x = X[l][j];
-        re -= r.re * x.re + r.im * x.im;
-        im -= r.re * x.im - r.im * x.re;
+  if (tid < 32) {
+    const double r = Rk[tid][tid].re;
+    rinv[tid] = tid < nb && r > 0.0 ? 1.0 / r : 0.0;
+  }
+  __syncthreads();
+  const int j = tid >> 3, s = tid & 7;
+  double xr[4], xi[4];  // solved rows s, s + 8, s + 16, s + 24 of column j
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    xr[q] = 0.0;
+    xi[q] = 0.0;
+  }
+  for (int i = 0; i < nb; ++i) {
+    // sum_{l < i} conj(Rk[l][i]) X[l][j], this lane's share
+    double pr = 0.0, pi = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int l = s + 8 * q;
+      if (l < i) {
+        const z64 r = Rk[l][i];
+        pr += r.re * xr[q] + r.im * xi[q];
+        pi += r.re * xi[q] - r.im * xr[q];
       }
-      const double rii = Rk[i][i].re;
-      X[i][j].re = rii > 0.0 ? re / rii : 0.0;
-      X[i][j].im = rii > 0.0 ? im / rii : 0.0;
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      pr += __shfl_xor(pr, o);
+      pi += __shfl_xor(pi, o);
+    }
+    const z64 b = X[i][j];
+    const double ri = rinv[i];
+    const double vr = (b.re - pr) * ri, vi = (b.im - pi) * ri;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (s + 8 * q == i) {
+        xr[q] = vr;
+        xi[q] = vi;
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int l = s + 8 * q;
+    if (l < nb) {
+      X[l][j].re = xr[q];
+      X[l][j].im = xi[q];
     }
   }
   __syncthreads();
   for (int e = tid; e < 1024; e += 256) {
-    const int i = e & 31, j = e >> 5;
-    if (i < nb && j < nc) G[(size_t)(c0 + j) * C + b0 + i] = X[i][j];
+    const int i = e & 31, jj = e >> 5;
+    if (i < nb && jj < nc) G[(size_t)(c0 + jj) * C + b0 + i] = X[i][jj];
   }
 }
 
 // Trailing update of the upper tiles (ti, tj), kb < ti <= tj: G -= R[kb, ti]^H R[kb, tj].
+// The two 32 x 32 blocks of R's block row and the output tile are staged through LDS with
+// coalesced column reads (G is column-major); four waves, each a 16 x 16 sub-tile on FP64
+// MFMA, subtract their products in LDS, and the tile is written back by columns.
 __global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ descs,
                                                    int kb) {
   const int g = blockIdx.y;
@@ -291,45 +331,50 @@ __global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ 
   z64* __restrict__ G = (z64*)descs[g].gram;
   const int b0 = kb * 32;
   const int nb = min(32, C - b0);
+  const int r0 = ti * 32, q0 = tj * 32;
+  const int ni = min(32, C - r0), nj = min(32, C - q0);
+  __shared__ z64 A[32][33];   // A[l][c] = R[b0 + l, r0 + c]
+  __shared__ z64 B[32][33];   // B[l][c] = R[b0 + l, q0 + c]
+  __shared__ z64 Gt[32][33];  // Gt[i][j] = G[r0 + i, q0 + j]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // unconditional loads from a clamped index (every matrix here has C <= 1024, so 32-bit
+  // element offsets), masked to zero outside the tile
+  const gptr<const z64> Gg = as_global((const z64*)G);
+  for (int e = tid; e < 1024; e += 256) {
+    const int l = e & 31, c = e >> 5;
+    const bool oka = l < nb && c < ni, okb = l < nb && c < nj, okg = l < ni && c < nj;
+    const uint32_t ia = oka ? (uint32_t)(r0 + c) * (uint32_t)C + b0 + l : 0u;
+    const uint32_t ib = okb ? (uint32_t)(q0 + c) * (uint32_t)C + b0 + l : 0u;
+    const uint32_t ig = okg ? (uint32_t)(q0 + c) * (uint32_t)C + r0 + l : 0u;
+    A[l][c] = cmask<double>(gload<double>(gat<double>(Gg, ia)), oka);
+    B[l][c] = cmask<double>(gload<double>(gat<double>(Gg, ib)), okb);
+    Gt[l][c] = cmask<double>(gload<double>(gat<double>(Gg, ig)), okg);
+  }
+  __syncthreads();
   const int col = lane & 15, grp = lane >> 4;
-  const int i0 = ti * 32 + (wave >> 1) * 16, j0 = tj * 32 + (wave & 1) * 16;
-  const int ci = i0 + col, cj = j0 + col;
+  const int i0 = (wave >> 1) * 16, j0 = (wave & 1) * 16;
   typedef Mfma<double>::v4 V4;
   V4 acc[2];
+#pragma unroll
   for (int v = 0; v < 4; ++v) {
     acc[0][v] = 0.0;
     acc[1][v] = 0.0;
   }
-  // the block row of R: 32 values per column, loaded together (out-of-range entries read
-  // entry b0 of column 0 and are masked)
-  const gptr<const z64> Gg = as_global((const z64*)G);
-  const uint32_t offi = (uint32_t)(ci < C ? ci : 0) * (uint32_t)C + b0;
-  const uint32_t offj = (uint32_t)(cj < C ? cj : 0) * (uint32_t)C + b0;
-  for (int l0 = 0; l0 < nb; l0 += 16) {
-    z64 xa[4], ya[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int l = l0 + 4 * u + grp;
-      const uint32_t lc = l < nb ? l : 0;
-      xa[u] = gload<double>(gat<double>(Gg, offi + lc));
-      ya[u] = gload<double>(gat<double>(Gg, offj + lc));
-    }
-    __builtin_amdgcn_sched_barrier(0);
+  for (int k0 = 0; k0 < 32; k0 += 4)
+    gram_mfma<double>(acc, A[k0 + grp][i0 + col], B[k0 + grp][j0 + col]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const bool lok = l0 + 4 * u + grp < nb;
-      gram_mfma<double>(acc, cmask<double>(xa[u], ci < C && lok),
-                        cmask<double>(ya[u], cj < C && lok));
-    }
-  }
   for (int v = 0; v < 4; ++v) {
-    const int i = i0 + Mfma<double>::row(lane, v), j = j0 + col;
-    if (i < C && j < C && i <= j) {
-      z64& z = G[(size_t)j * C + i];
-      z.re -= acc[0][v];
-      z.im -= acc[1][v];
-    }
+    z64& z = Gt[i0 + Mfma<double>::row(lane, v)][j0 + col];
+    z.re -= acc[0][v];
+    z.im -= acc[1][v];
+  }
+  __syncthreads();
+  const gptr<z64> Gw = as_global(G);
+  for (int e = tid; e < 1024; e += 256) {
+    const int i = e & 31, j = e >> 5;
+    if (i < ni && j < nj && r0 + i <= q0 + j)
+      gstore<double>(gat<double>(Gw, (uint32_t)(q0 + j) * (uint32_t)C + r0 + i), Gt[i][j]);
   }
 }
 

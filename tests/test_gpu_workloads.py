@@ -17,6 +17,13 @@ pytestmark = pytest.mark.gpu
 # error of the gauge-invariant two-site tensor.  eps is a sum of sigma^2 (discarded ones, or
 # 1 - the kept ones), so |d eps| <= 2 sum_j sigma_j |d sigma_j| <= 2 lam sigma_1 sum_j sigma_j.
 TOL32 = dict(lam=2e-5, th=5e-5)
+# The truncated two-site tensor is the best rank-k approximation of theta, and the kept
+# singular subspace moves by ||E|| / (sigma_k - sigma_{k+1}) under a perturbation E of theta
+# (Wedin): the truncated tensor moves by at most about ||E|| (1 + 2 sigma_k / (sigma_k -
+# sigma_{k+1})).  Where the spectrum is nearly degenerate at the cut (the truncation of a
+# 1024 x 1024 theta to 512 in the 2D circuit has relative gaps ~2e-4), the bound uses the FP32
+# path's relative backward error, taken as BACKWARD32 (measured ~3e-7).
+BACKWARD32 = 1e-6
 
 
 def _two_site(gq, lam_l, lam_m, gq1, lam_r):
@@ -40,8 +47,14 @@ def _check_bond(m, s, q, gate, before, st_k, st_eps, chi, label, reading="litera
     th_ref = _two_site(local.gam[0], l0, local.lam[1], local.gam[1], l2)
     th_gpu = _two_site(m.export_site(q, s), l0, lam_gpu, m.export_site(q + 1, s), l2)
     err = np.linalg.norm(th_gpu - th_ref) / np.linalg.norm(th_ref)
-    say(f"    two-site rel. error {err:.2e}")
-    assert err <= TOL32["th"]
+    sig, k = ref["sigma"], ref["k"]
+    amp = 1.0
+    if k < len(sig) and sig[k - 1] > sig[k]:
+        amp = 1.0 + 2.0 * sig[k - 1] / (sig[k - 1] - sig[k])
+    tol = max(TOL32["th"], BACKWARD32 * amp)
+    gap = (sig[k - 1] - sig[k]) / sig[0] if k < len(sig) else float("nan")
+    say(f"    two-site rel. error {err:.2e} (boundary gap {gap:.2e} sigma_1, tolerance {tol:.2e})")
+    assert err <= tol
 
 
 def _export_bond(m, s, q):
