@@ -60,6 +60,10 @@ def parse_args(argv=None):
                    help="skip the canonicalize + sampling measurement")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="target CPU seconds for the oracle sample")
+    p.add_argument("--autotune-cache", default=os.path.join(ROOT, "paper_2312_02667_amd",
+                                                              "autotune_cache.json"),
+                   help="SVD schedule cache written by paper_2312_02667_amd.autotune; the entry "
+                        "for the workload's shape, if any, is applied (empty: none)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="first run a plain elementwise copy kernel (MIB MiB read, MIB MiB "
                         "written) three times, a kernel of known traffic for scaling hardware "
@@ -72,12 +76,18 @@ def setup_layers(chi: int) -> int:
     return int(math.ceil(math.log2(chi))) + 1
 
 
-def run_path(precision, layers, n_setup, warmup, steps, n_sites, chi, stream):
+def run_path(precision, layers, n_setup, warmup, steps, n_sites, chi, stream,
+             autotune_cache=""):
     import torch
 
-    from paper_2312_02667_amd import ptebd
+    from paper_2312_02667_amd import autotune, ptebd
 
     m = ptebd.MPS(n_sites, chi, precision, stream=stream)
+    tuned = None
+    if autotune_cache:
+        key, params = autotune.apply(m, autotune_cache, chi, len(layers[-1][0]))
+        tuned = {"cache": os.path.relpath(autotune_cache, ROOT), "key": key, "params": params}
+        log(f"[{precision}] autotuned SVD schedule {key}: {params}")
     for i in range(n_setup + warmup):
         bonds, gates = layers[i]
         st = m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12, eps_reading=EPS_READING)
@@ -104,7 +114,8 @@ def run_path(precision, layers, n_setup, warmup, steps, n_sites, chi, stream):
     kstats = m.kernel_stats()
     m.set_profiling(False)
     return m, {"value": n_updates / elapsed, "elapsed_s": elapsed, "updates": n_updates,
-               "ms_per_step": 1e3 * elapsed / steps, "kernels": kstats, "layers": per_layer}
+               "ms_per_step": 1e3 * elapsed / steps, "kernels": kstats, "layers": per_layer,
+               "autotune": tuned, "svd_params": m.svd_params()}
 
 
 def measured_traffic(kernel_name: str, precision: str):
@@ -254,7 +265,7 @@ def main(argv=None):
         f"timed {args.steps})")
 
     mixed_m, mixed = run_path(args.precision, layers, n_setup, args.warmup, args.steps, n, chi,
-                              stream)
+                              stream, args.autotune_cache)
     result = {
         "metric": METRIC, "value": mixed["value"], "unit": "bond updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"],
@@ -268,6 +279,8 @@ def main(argv=None):
                    "n_sites": n, "chi_max": chi, "depth": depth, "seed": args.seed,
                    "precision": args.precision},
         "roofline": roofline(mixed["kernels"], args.precision),
+        "autotune": mixed["autotune"],
+        "svd_params": mixed["svd_params"],
         "kernels": mixed["kernels"],
         "layers": mixed["layers"],
     }
@@ -275,12 +288,14 @@ def main(argv=None):
     result["norm_estimate"] = mixed_m.norm_estimate()
     result["fidelity_estimate"] = mixed_m.fidelity_estimate()
     if not args.no_fp64 and args.precision != "fp64":
-        f64_m, f64 = run_path("fp64", layers, n_setup, args.warmup, args.steps, n, chi, stream)
+        f64_m, f64 = run_path("fp64", layers, n_setup, args.warmup, args.steps, n, chi, stream,
+                              args.autotune_cache)
         ov = mixed_m.overlap(f64_m)
         n1, n2 = mixed_m.norm(), f64_m.norm()
         err_f = 1.0 - abs(ov) ** 2 / (n1 ** 2 * n2 ** 2)
         result["fp64_gpu"] = {"value": f64["value"], "ms_per_step": f64["ms_per_step"],
                               "roofline": roofline(f64["kernels"], "fp64"),
+                              "autotune": f64["autotune"], "svd_params": f64["svd_params"],
                               "layers": f64["layers"]}
         result["speedup_vs_fp64_gpu"] = mixed["value"] / f64["value"]
         result["err_F_vs_fp64_gpu"] = err_f

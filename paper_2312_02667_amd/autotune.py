@@ -1,0 +1,249 @@
+"""Autotuner for the batched SVD's schedule, with a JSON cache.
+
+The Jacobi SVD of a layer has per-handle controls (``ptebd_set_svd_params``): the number of
+inner sweeps per block pair and the cosine above which another one follows, the ordering of
+each rotated pair's columns by norm, the split of a large batch over two streams, and (FP32)
+the Cholesky preconditioning.  Which schedule is fastest depends on the shape of the work:
+the theta size (twice the bond dimension) and how many gates one batch holds.  The tuner
+times candidate schedules on one fixed input of that shape and keeps the fastest one that
+
+* converges (no gate reaches the sweep cap), and
+* gives the same bond weights as the default schedule to within the precision's tolerance
+  (every candidate computes the same SVD; only the rounding path differs),
+
+then stores it in a JSON cache keyed by precision, theta size and batch-size bucket.
+``lookup`` / ``apply`` read the cache back for a handle.
+
+The search is coordinate descent from the defaults: each control in turn takes every value
+of its candidate list with the others held, and the best point found so far is kept; two
+passes.  The search itself (``search``) only sees an evaluation function, so it runs without
+a GPU; ``measure_layer_schedule`` is the GPU evaluation over the C ABI.
+
+Command line (one MI355X)::
+
+    python -m paper_2312_02667_amd.autotune --n-sites 1024 --chi 256 --precision fp32 \\
+        --cache paper_2312_02667_amd/autotune_cache.json
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+# The controls the tuner may move and their candidate values.  tol_factor and max_sweeps
+# are accuracy controls and stay at the caller's values.
+SEARCH_SPACE = {
+    "inner_sweeps": (1, 2, 3),
+    "inner_repeat": (3e-3, 1e-2, 3e-2),
+    "sort_pairs": (0, 1),
+    "streams": (1, 2),
+    "precondition": (0, 1),
+}
+
+# Largest allowed |Lambda_candidate - Lambda_default| / Lambda_default[0] over all bonds.
+LAMBDA_TOL = {"fp32": 2e-5, "fp64": 1e-10}
+
+CACHE_VERSION = 1
+
+
+def cache_key(precision: str, chi: int, n_gates: int) -> str:
+    """Theta of a saturated bond is (2 chi) x (2 chi); batches are bucketed by powers of 2."""
+    bucket = 1 << max(0, int(math.ceil(math.log2(max(1, n_gates)))))
+    return f"{precision}/theta{2 * int(chi)}/gates{bucket}"
+
+
+def _space_for(precision: str) -> dict:
+    space = dict(SEARCH_SPACE)
+    if precision != "fp32":
+        space.pop("precondition")  # the FP64 path is not preconditioned
+    return space
+
+
+def _canon(params: dict, space: dict) -> tuple:
+    return tuple((k, params[k]) for k in sorted(space))
+
+
+def search(evaluate, defaults: dict, space: dict, passes: int = 2, min_gain: float = 0.01):
+    """Coordinate descent.  ``evaluate(params) -> dict(ms=float, ok=bool, ...)``; ``ok`` is
+    False for a candidate that did not converge or moved the bond weights.  A candidate
+    replaces the best point only when it is faster by more than the fraction ``min_gain``
+    (run-to-run noise of a layer's device time is below 1 %), so the defaults stay unless
+    something is clearly better.  Returns (best_params, best_result, history) with history a
+    list of (params, result)."""
+    seen = {}
+    history = []
+
+    def run(p):
+        key = _canon(p, space)
+        if key not in seen:
+            r = evaluate(dict(p))
+            seen[key] = r
+            history.append((dict(p), r))
+        return seen[key]
+
+    best = {k: defaults[k] for k in space}
+    best_r = run(best)
+    if not best_r["ok"]:
+        raise RuntimeError("the default schedule itself failed the checks")
+    for _ in range(passes):
+        improved = False
+        for name, values in space.items():
+            for v in values:
+                if v == best[name]:
+                    continue
+                cand = dict(best)
+                cand[name] = v
+                # inner_repeat only matters when a second inner sweep can follow
+                if cand["inner_sweeps"] == 1 and name == "inner_repeat":
+                    continue
+                r = run(cand)
+                if r["ok"] and r["ms"] < best_r["ms"] * (1.0 - min_gain):
+                    best, best_r, improved = cand, r, True
+        if not improved:
+            break
+    return best, best_r, history
+
+
+def load_cache(path: str) -> dict:
+    if not path or not os.path.exists(path):
+        return {"version": CACHE_VERSION, "entries": {}}
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("version") != CACHE_VERSION or not isinstance(data.get("entries"), dict):
+        raise ValueError(f"{path}: not an autotuner cache of version {CACHE_VERSION}")
+    return data
+
+
+def save_cache(path: str, data: dict) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+        f.write("\n")
+    os.replace(tmp, path)
+
+
+def lookup(cache: dict, precision: str, chi: int, n_gates: int):
+    """The cached schedule for this shape, or None."""
+    e = cache.get("entries", {}).get(cache_key(precision, chi, n_gates))
+    return dict(e["params"]) if e else None
+
+
+def apply(mps, cache_path: str, chi: int, n_gates: int):
+    """Set the cached schedule on a handle; returns (key, params) or (key, None) if the cache
+    holds nothing for the shape (the handle keeps its schedule)."""
+    key = cache_key(mps.precision, chi, n_gates)
+    params = lookup(load_cache(cache_path), mps.precision, chi, n_gates)
+    if params:
+        mps.set_svd_params(**params)
+    return key, params
+
+
+def measure_layer_schedule(n_sites: int, chi: int, precision: str, seed: int = 0,
+                           timed_layers: int = 3, repeats: int = 1):
+    """Build the GPU evaluation for ``search``: a Haar brickwork chain of n_sites is driven
+    (default schedule) to the layer where every bulk bond is at chi, its state is kept, and
+    each candidate then applies the same ``timed_layers`` layers to a fresh copy of it.  The
+    result holds the summed device time of those layers (the least over ``repeats``), the
+    largest sweep count and whether the checks passed.  Returns (evaluate, defaults,
+    n_gates)."""
+    import numpy as np
+
+    from . import inputs, ptebd
+
+    setup = max(1, int(math.ceil(math.log2(max(2, chi))))) + 1
+    layers = inputs.brickwork_circuit(n_sites, setup + timed_layers, seed)
+    m = ptebd.MPS(n_sites, chi, precision)
+    defaults = m.svd_params()
+    for i in range(setup):
+        m.apply_layer(*layers[i], chi_max=chi)
+    gam, lam = m.export()
+    m.close()
+    timed = layers[setup:]
+    ref = {}
+
+    def evaluate(params):
+        best_ms, lam_end, sweeps, unconv = None, None, 0, 0
+        for _ in range(max(1, repeats)):
+            h = ptebd.MPS(n_sites, chi, precision)
+            h.import_state(gam, lam)
+            h.set_svd_params(**params)
+            ms = 0.0
+            for bonds, gates in timed:
+                st = h.apply_layer(bonds, gates, chi_max=chi)
+                ms += st["device_ms"]
+                sweeps = max(sweeps, int(st["max_sweeps"]))
+                unconv += int(st["n_unconverged"])
+            lam_end = [h.get_lambda(q) for q in range(n_sites + 1)]
+            h.close()
+            best_ms = ms if best_ms is None else min(best_ms, ms)
+        if not ref:
+            ref["lam"] = lam_end  # the first evaluation is the default schedule
+        dev = max(float(np.max(np.abs(a - b))) / float(b[0]) if len(a) == len(b) else math.inf
+                  for a, b in zip(lam_end, ref["lam"]))
+        ok = unconv == 0 and dev <= LAMBDA_TOL[precision]
+        return {"ms": best_ms, "ok": ok, "max_sweeps": sweeps, "lambda_dev": dev,
+                "n_unconverged": unconv}
+
+    n_gates = len(timed[0][0])
+    return evaluate, {k: defaults[k] for k in SEARCH_SPACE if k in defaults}, n_gates
+
+
+def tune(n_sites: int, chi: int, precision: str, cache_path: str, seed: int = 0,
+         timed_layers: int = 3, repeats: int = 1, passes: int = 2, log=print,
+         min_gain: float = 0.01) -> dict:
+    """Tune one shape on the GPU and store the result in the cache; returns the entry."""
+    evaluate, defaults, n_gates = measure_layer_schedule(n_sites, chi, precision, seed,
+                                                         timed_layers, repeats)
+    space = _space_for(precision)
+
+    def logged(p):
+        r = evaluate(p)
+        log(json.dumps({"params": p, **r}))
+        return r
+
+    best, best_r, history = search(logged, defaults, space, passes, min_gain)
+    base_r = history[0][1]
+    entry = {
+        "params": best,
+        "ms": best_r["ms"],
+        "default_ms": base_r["ms"],
+        "default_params": history[0][0],
+        "min_gain": min_gain,
+        "workload": f"Haar brickwork, N={n_sites}, chi={chi}, {timed_layers} saturated layers "
+                    f"of {n_gates} gates, seed {seed}",
+        "evaluated": [{"params": p, "ms": r["ms"], "ok": r["ok"],
+                       "lambda_dev": r["lambda_dev"], "max_sweeps": r["max_sweeps"]}
+                      for p, r in history],
+        "time": time.strftime("%Y-%m-%d %H:%M:%S"),
+    }
+    cache = load_cache(cache_path)
+    cache["entries"][cache_key(precision, chi, n_gates)] = entry
+    save_cache(cache_path, cache)
+    return entry
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--n-sites", type=int, default=1024)
+    ap.add_argument("--chi", type=int, nargs="+", default=[256])
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--cache", default=os.path.join(os.path.dirname(__file__),
+                                                    "autotune_cache.json"))
+    ap.add_argument("--timed-layers", type=int, default=3)
+    ap.add_argument("--repeats", type=int, default=1)
+    ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--min-gain", type=float, default=0.01)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    for chi in a.chi:
+        e = tune(a.n_sites, chi, a.precision, a.cache, a.seed, a.timed_layers, a.repeats,
+                 a.passes, log=lambda s: print(s, flush=True), min_gain=a.min_gain)
+        print(json.dumps({"chi": chi, "best": e["params"], "ms": e["ms"],
+                          "default_ms": e["default_ms"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
