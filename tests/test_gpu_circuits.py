@@ -58,8 +58,8 @@ def test_mixed_path_ragged_caps(precision, chi):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_two_streams_bit_identical(precision):
-    """A layer of >= 64 bond updates runs its Jacobi sweeps on two streams (half the gates
-    each) by default; one stream must give bitwise the same state."""
+    """A batch of >= 64 bond updates (a layer, or a PtSU half-step) runs as two halves on two
+    streams by default; one stream must give bitwise the same state."""
     n, depth, chi = 200, 9, 32
     layers = inputs.brickwork_circuit(n, depth, seed=21)
     a = ptebd.MPS(n, chi, precision)
@@ -70,6 +70,12 @@ def test_two_streams_bit_identical(precision):
         sa = a.apply_layer(bonds, gates, chi_max=chi)
         sb = b.apply_layer(bonds, gates, chi_max=chi)
         assert len(bonds) >= 64
+        assert np.array_equal(sa["sweeps"], sb["sweeps"])
+    # truncating layers followed by PtSU: its half-steps (199 and 200 updates) split too
+    for bonds, gates in inputs.brickwork_circuit(n, 2, seed=22):
+        sa = a.apply_layer(bonds, gates, chi_max=chi, ptsu_steps=2)
+        sb = b.apply_layer(bonds, gates, chi_max=chi, ptsu_steps=2)
+        assert sa["triggered"] and sa["ptsu_done"] == 2 and sb["ptsu_done"] == 2
         assert np.array_equal(sa["sweeps"], sb["sweeps"])
     ga, la = a.export()
     gb, lb = b.export()
