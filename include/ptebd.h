@@ -138,11 +138,14 @@ typedef struct {
                            Haar bonds, and no right-vector accumulation).  FP64 handles ignore
                            it: the Gram matrix would square the condition number and cost the
                            relative accuracy of the FP64 path. */
-  int streams;          /* 1 or 2, default 2: with 2, a batch of at least 64 bond updates runs
-                           its Jacobi sweeps on two HIP streams, half the gates each (the
-                           second stream is the library's own, default priority), so that one
-                           half's rounds fill the GPU while the other's launches drain; both
-                           halves join at every sweep.  Results are the same bit for bit. */
+  int streams;          /* 1 or 2, default 2: with 2, a batch of at least 64 bond updates is
+                           split into two halves, each run end to end (theta, preconditioning,
+                           Jacobi sweeps, finalize, write-back) on its own HIP stream (the
+                           second one is the library's own, default priority); each half
+                           sweeps until its own gates have converged, so one half's work
+                           fills the GPU while the other's launches drain.  The call returns
+                           once both streams have drained.  Results are the same bit for
+                           bit as with 1. */
 } ptebd_svd_params;
 
 /* Read (get) or replace (set) the SVD controls of a handle.  set validates every field

@@ -422,6 +422,14 @@ int run_split(ptebd_mps* h, const SplitStreams& sp, const GateDesc* d_desc,
   // the second stream starts after everything already queued on the first
   PT_HIP(hipEventRecord(sp.ev_fork, stream));
   PT_HIP(hipStreamWaitEvent(sp.s2, sp.ev_fork, 0));
+  // whatever way this returns, neither stream is left running on the batch's buffers
+  struct Drain {
+    hipStream_t a, b;
+    ~Drain() {
+      (void)hipStreamSynchronize(a);
+      (void)hipStreamSynchronize(b);
+    }
+  } drain{stream, sp.s2};
   auto front = [&](int k) {
     const GateDesc* dd = d_desc + off[k];
     timed(pf, PTEBD_KERNEL_THETA, st[k], [&] { ptebd::launch_theta<T>(dd, nn[k], max_tiles, st[k]); });
