@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
 
   __shared__ cplx<T> G[32][33];
   __shared__ cplx<T> Q[32][33];
-  __shared__ T P[16][4];  // one round's rotations: c, Re s, Im s
+  __shared__ __align__(16) T P[16][4];  // one round's rotations: c, Re s, Im s, (unused)
   __shared__ T Qs[32][33];  // Re + Im of the permuted Q
   __shared__ double red[4];
   __shared__ unsigned int rmax_bits;  // largest |g|^2 / (a b) rotated in this inner sweep
@@ -503,10 +503,45 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   // Another inner sweep follows only while the last one still rotated a pair whose cosine
   // exceeded inner_repeat: cyclic Jacobi converges quadratically, so after a sweep whose
   // largest rotated cosine was c the remaining ones are of order c^2.
+  // One round's rotation as one 16-byte LDS access (two for FP64) each way.
+  auto put_rot = [&](int k, double c, double sr, double si) {
+    if constexpr (sizeof(T) == 4) {
+      vf4 w;
+      w.x = (float)c;
+      w.y = (float)sr;
+      w.z = (float)si;
+      w.w = 0.f;
+      *reinterpret_cast<vf4*>(&P[k][0]) = w;
+    } else {
+      vd2 w0, w1;
+      w0.x = c;
+      w0.y = sr;
+      w1.x = si;
+      w1.y = 0.0;
+      *reinterpret_cast<vd2*>(&P[k][0]) = w0;
+      *reinterpret_cast<vd2*>(&P[k][2]) = w1;
+    }
+  };
+  auto get_rot = [&](int k, T& c, T& sr, T& si) {
+    if constexpr (sizeof(T) == 4) {
+      const vf4 r = *reinterpret_cast<const vf4*>(&P[k][0]);
+      c = r.x;
+      sr = r.y;
+      si = r.z;
+    } else {
+      const vd2 r0 = *reinterpret_cast<const vd2*>(&P[k][0]);
+      const vd2 r1 = *reinterpret_cast<const vd2*>(&P[k][2]);
+      c = r0.x;
+      sr = r0.y;
+      si = r1.x;
+    }
+  };
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     __syncthreads();
     if (tid == 0) rmax_bits = 0u;
     __syncthreads();
+    // the largest squared cosine this thread's pair rotated in the sweep, published once
+    float my_rmax = 0.f;
     for (int rd = 0; rd < 31; ++rd) {
       const cplx<T> b00 = G[ra][ca0], b01 = G[ra][cb2], b10 = G[rb2][ca0], b11 = G[rb2][cb2];
       const cplx<T> q00 = Q[ra][ca0], q01 = Q[ra][cb2], q10 = Q[rb2][ca0], q11 = Q[rb2][cb2];
@@ -520,15 +555,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
           const double ab = gpp * gqq;
           const float cos2 =
               ab > 0.0 ? (float)((gr * gr + gi * gi) * __builtin_amdgcn_rcp(ab)) : 3.0e38f;
-          atomicMax(&rmax_bits, __float_as_uint(cos2));
+          my_rmax = fmaxf(my_rmax, cos2);
         }
-        P[ia][0] = (T)c;
-        P[ia][1] = (T)sr;
-        P[ia][2] = (T)si;
+        put_rot(ia, c, sr, si);
       }
       __syncthreads();
-      const T ca = P[ia][0], sar = P[ia][1], sai = P[ia][2];
-      const T cb = P[ib][0], sbr = P[ib][1], sbi = P[ib][2];
+      T ca, sar, sai, cb, sbr, sbi;
+      get_rot(ia, ca, sar, sai);
+      get_rot(ib, cb, sbr, sbi);
       // X = B J_b: X[:,0] = c_b B[:,0] - conj(s_b) B[:,1];  X[:,1] = s_b B[:,0] + c_b B[:,1]
       cplx<T> x00, x01, x10, x11;
       x00.re = cb * b00.re - (sbr * b01.re + sbi * b01.im);
@@ -569,6 +603,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
       Q[rb2][ncb] = m11;
       __syncthreads();
     }
+    if (diag_owner && my_rmax > 0.f) atomicMax(&rmax_bits, __float_as_uint(my_rmax));
+    __syncthreads();
     const float rmax2 = __uint_as_float(rmax_bits);
     if (!(rmax2 > (float)(inner_repeat * inner_repeat)) || rmax_bits == 0u) break;
   }
