@@ -85,6 +85,36 @@ def test_two_streams_bit_identical(precision):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_sweep_cap_warning_split_and_single_stream(precision):
+    """A layer whose SVDs hit the sweep cap returns the WNOCONV warning with the count of
+    unconverged gates; the split batch reports the same count and the same state as one
+    stream, and the state stays finite."""
+    n, chi = 200, 32
+    layers = inputs.brickwork_circuit(n, 8, seed=23)
+    a = ptebd.MPS(n, chi, precision)
+    b = ptebd.MPS(n, chi, precision)
+    b.set_svd_params(streams=1)
+    for bonds, gates in layers[:7]:
+        a.apply_layer(bonds, gates, chi_max=chi)
+        b.apply_layer(bonds, gates, chi_max=chi)
+    for m in (a, b):
+        m.set_svd_params(max_sweeps=2)
+    bonds, gates = layers[7]
+    sa = a.apply_layer(bonds, gates, chi_max=chi)
+    sb = b.apply_layer(bonds, gates, chi_max=chi)
+    assert sa["status"] == ptebd.WNOCONV and sb["status"] == ptebd.WNOCONV
+    assert sa["n_unconverged"] > 0 and sa["n_unconverged"] == sb["n_unconverged"]
+    assert int(np.max(sa["sweeps"])) == 2 and np.array_equal(sa["sweeps"], sb["sweeps"])
+    ga, la = a.export()
+    gb, lb = b.export()
+    assert all(np.array_equal(x, y) for x, y in zip(la, lb))
+    assert all(np.array_equal(x, y) for x, y in zip(ga, gb))
+    assert all(np.all(np.isfinite(x)) for x in la)
+    a.close()
+    b.close()
+
+
 def test_batched_states_match_separate_runs():
     """Three circuits of different N and chi_max in one handle (one launch per layer over all
     of them) give bitwise the same states as three separate handles."""
