@@ -80,9 +80,11 @@ __device__ inline bool jacobi_rotation(double a, double b, double gr, double gi,
 // M_st = A_s B_t, A_s = diag(Lambda[q]) Gamma[q]_s diag(Lambda[q+1]) (chi_q x chi_{q+1}),
 // B_t = Gamma[q+1]_t diag(Lambda[q+2]) (chi_{q+1} x chi_{q+2}), then mixes them with the
 // gate: theta[(s',a),(t',c)] = sum_st U[(s't'),(st)] M_st[a,c].  Four waves, each a 16x16
-// sub-tile of all four products; K (= chi_{q+1}) staged through LDS in steps of 16.
+// sub-tile of all four products; K (= chi_{q+1}) staged through LDS in steps of 16.  Built
+// for four waves per SIMD in FP32 (the three-product form's third accumulators fit without
+// spills) and two in FP64.
 template <class T>
-__global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void theta_kernel(const GateDesc* __restrict__ descs) {
   const GateDesc* d = descs + blockIdx.y;
   const int cl = d->cl, cm = d->cm, cr = d->cr;
   const int tiles_c = (cr + 31) >> 5;
@@ -96,10 +98,29 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave >> 1, wc = wave & 1;
   typedef typename Mfma<T>::v4 V4;
-  V4 acc[4][2];
+  // FP32: three real products per complex one: for a = x + iy, b = u + iv the MFMAs
+  // accumulate P1 = x u, P2 = y v and P3 = (x + y)(u + v); Re ab = P1 - P2,
+  // Im ab = P3 - P1 - P2.  FP64 keeps the four-product form (acc[.][0] = Re, acc[.][1] = Im):
+  // the third accumulator would halve its occupancy.
+  constexpr bool k3 = sizeof(T) == 4;
+  V4 acc[4][3];
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 3; ++j)
       for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+  auto mfma3 = [](V4(&c)[3], cplx<T> a, T as, cplx<T> b, T bs) {
+    if constexpr (k3) {
+      c[0] = Mfma<T>::op(a.re, b.re, c[0]);
+      c[1] = Mfma<T>::op(a.im, b.im, c[1]);
+      c[2] = Mfma<T>::op(as, bs, c[2]);
+    } else {
+      (void)as;
+      (void)bs;
+      V4 two[2] = {c[0], c[1]};
+      cmfma<T>(two, a, b);
+      c[0] = two[0];
+      c[1] = two[1];
+    }
+  };
 
   const gptr<const cplx<T>> __restrict__ gq = as_global((const cplx<T>*)d->gq);
   const gptr<const cplx<T>> __restrict__ gq1 = as_global((const cplx<T>*)d->gq1);
@@ -145,10 +166,12 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
       const cplx<T> a1v = As[1][kk][wa * 16 + (lane & 15)];
       const cplx<T> b0v = Bs[0][kk][wc * 16 + (lane & 15)];
       const cplx<T> b1v = Bs[1][kk][wc * 16 + (lane & 15)];
-      cmfma<T>(acc[0], a0v, b0v);
-      cmfma<T>(acc[1], a0v, b1v);
-      cmfma<T>(acc[2], a1v, b0v);
-      cmfma<T>(acc[3], a1v, b1v);
+      const T a0s = a0v.re + a0v.im, a1s = a1v.re + a1v.im;
+      const T b0s = b0v.re + b0v.im, b1s = b1v.re + b1v.im;
+      mfma3(acc[0], a0v, a0s, b0v, b0s);
+      mfma3(acc[1], a0v, a0s, b1v, b1s);
+      mfma3(acc[2], a1v, a1s, b0v, b0s);
+      mfma3(acc[3], a1v, a1s, b1v, b1s);
     }
     __syncthreads();
   }
@@ -168,8 +191,13 @@ __global__ __launch_bounds__(256) void theta_kernel(const GateDesc* __restrict__
     if (a >= cl || c >= cr) continue;
     T mr[4], mi[4];
     for (int st = 0; st < 4; ++st) {
-      mr[st] = acc[st][0][v];
-      mi[st] = acc[st][1][v];
+      if constexpr (k3) {
+        mr[st] = acc[st][0][v] - acc[st][1][v];
+        mi[st] = acc[st][2][v] - acc[st][0][v] - acc[st][1][v];
+      } else {
+        mr[st] = acc[st][0][v];
+        mi[st] = acc[st][1][v];
+      }
     }
     for (int sp = 0; sp < 2; ++sp) {
       for (int tp = 0; tp < 2; ++tp) {
