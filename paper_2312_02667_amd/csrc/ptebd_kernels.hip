@@ -471,19 +471,29 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   // inner rotations below do not use this test, so a pair the measure counts is always
   // rotated.
   constexpr double tiny = sizeof(T) == 4 ? 9.094947017729282e-13 : 3.1554436208840472e-30;
+  // FP32: the largest squared cosine |G_ij|^2 / (G_ii G_jj), one square root at the end
+  // (the entries are FP32 values, so their squares and products are normal FP64 numbers).
+  // FP64 entries may be small enough for their squares to underflow: scaled hypot there.
+  constexpr bool kSq = sizeof(T) == 4;
   double mx = 0.0;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
     if (i < j) {
       const double di = (double)G[i][i].re, dj = (double)G[j][j].re;
-      if (fmin(di, dj) > tiny * fmax(di, dj))
-        mx = fmax(mx, hypot((double)G[i][j].re, (double)G[i][j].im) / sqrt(di * dj));
+      if (fmin(di, dj) > tiny * fmax(di, dj)) {
+        const double gr = (double)G[i][j].re, gi = (double)G[i][j].im;
+        if constexpr (kSq)
+          mx = fmax(mx, (gr * gr + gi * gi) / (di * dj));
+        else
+          mx = fmax(mx, hypot(gr, gi) / sqrt(di * dj));
+      }
     }
   }
   mx = wave_max(mx);
   if (lane == 0) red[wave] = mx;
   __syncthreads();
   mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if constexpr (kSq) mx = sqrt(mx);
   const bool rotate = mx > tol_scale * sqrt((double)R);
   if (tid == 0) {
     atomicMax(&out.offbits[g], __float_as_uint((float)mx));
