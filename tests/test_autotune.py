@@ -124,3 +124,21 @@ def test_noise_level_gains_do_not_move_the_schedule():
     assert best == DEFAULTS
     best, _, _ = autotune.search(evaluate, DEFAULTS, space, min_gain=0.0)
     assert best != DEFAULTS
+
+
+def test_committed_cache_is_valid():
+    """The cache shipped with the package (applied by the benchmark) loads, every entry's
+    schedule lies in the search space of its precision, and the benchmark's shape has one."""
+    import os
+    path = os.path.join(os.path.dirname(autotune.__file__), "autotune_cache.json")
+    cache = autotune.load_cache(path)
+    assert cache["entries"]
+    for key, e in cache["entries"].items():
+        precision = key.split("/")[0]
+        space = autotune._space_for(precision)
+        assert set(e["params"]) == set(space), key
+        for k, v in e["params"].items():
+            assert v in space[k], (key, k, v)
+        assert e["ms"] <= e["default_ms"] and e["evaluated"], key
+    assert autotune.lookup(cache, "fp32", 256, 512) is not None
+    assert autotune.lookup(cache, "fp64", 256, 511) is not None
