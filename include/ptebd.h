@@ -57,6 +57,13 @@ extern "C" {
 #define PTEBD_FP32 1  /* Gamma, theta, Jacobi column updates in FP32 (FP32 MFMA); the
                          Jacobi rotation angles, singular values, eps, nu, Lambda and
                          the Lambda^{-1} divisions in FP64 */
+#define PTEBD_BF16X3 2 /* contractions on bf16 MFMA with each FP32 operand split into
+                          hi = bf16(x), lo = bf16(x - hi) and the products hi hi + hi lo + lo hi
+                          accumulated in FP32.  Not built in this library: every call that
+                          takes a precision returns PTEBD_EINVAL for it.  The split keeps
+                          ~16 mantissa bits, so the Jacobi column updates could not use it
+                          at a 1e-6 fidelity budget, and the theta contraction it would speed
+                          up is a few per cent of a layer. */
 
 /* On the FP32 path every truncation (gates and tSU) drops the singular values
  * sigma <= max(cutoff, PTEBD_FP32_CUTOFF_FLOOR) sigma_1.  The exact zeros of a rank-deficient
@@ -68,14 +75,16 @@ extern "C" {
 #define PTEBD_FP32_CUTOFF_FLOOR 1.9073486328125e-06
 
 /* ------------------------------------------------------------------ layer flags */
-#define PTEBD_FLAG_NO_STABILIZE 1  /* nu_i = 1 (norm-stabilization ablation, Sec. III.C.1) */
+#define PTEBD_FLAG_NO_STABILIZE 1  /* nu_i = 1 (norm-stabilization ablation: the norm decay of
+                                      Sec. III.C.1 without the remedy of Sec. III.C.2) */
 #define PTEBD_FLAG_RELATIVE_EPS 2  /* eps_i = discarded sigma^2 / sum sigma^2 (keeps each bond's
                                       local norm); default: the literal discarded sigma^2 */
 #define PTEBD_FLAG_COMPLEMENT_EPS 4 /* eps_i = 1 - kept sigma^2, so that nu_i rescales the kept
                                       values to unit norm.  All three readings of Theorem 1's
                                       local error agree on a normalized canonical input; this
                                       one keeps the stabilized norm near 1 over long circuits
-                                      (Sec. V.B), the literal one lets it grow under heavy
+                                      (the norm-vs-depth result of Sec. IV.B, numerical
+                                      stability), the literal one lets it grow under heavy
                                       truncation.  Not combinable with RELATIVE_EPS. */
 
 typedef struct ptebd_mps* ptebd_mps_t;
@@ -85,8 +94,10 @@ typedef struct ptebd_mps* ptebd_mps_t;
 typedef struct {
   int32_t* k;       /* kept bond dimension of each gate's bond */
   int32_t* rank;    /* r = #{sigma > cutoff * sigma_1} */
-  double* eps;      /* discarded weight eps_i = sum of the dropped sigma^2 (Theorem 1) */
-  double* nu;       /* stabilization factor applied to Lambda[q+1] */
+  double* eps;      /* local truncation error eps_i of Theorem 1 under the chosen reading
+                       (default: the sum of the dropped sigma^2) */
+  double* nu;       /* stabilization factor applied to Lambda[q+1]: (1 - eps_i)^(-1/2) when
+                       the layer was compressed and stabilization is on, else exactly 1 */
   int32_t* sweeps;  /* Jacobi sweeps used by the gate's SVD */
   int32_t triggered;      /* 1 if some gate had r > chi_max (the layer was compressed) */
   int32_t ptsu_done;      /* PtSU steps executed after the gates */
@@ -108,7 +119,7 @@ const char* ptebd_last_error(void);
  *   chi_cap[s]  in [1, 512], largest bond dimension state s may reach (sizes its device slots:
  *               N * 2 * chi_cap^2 complex numbers of the chosen precision);
  *   d           local dimension, must be 2;
- *   precision   PTEBD_FP64 or PTEBD_FP32;
+ *   precision   PTEBD_FP64 or PTEBD_FP32 (PTEBD_BF16X3: EINVAL, not built);
  *   hip_stream  hipStream_t every device operation of the handle is ordered on
  *               (NULL = the null stream); the library does not own it.
  * Errors: EINVAL, ENOMEM, EDEVICE.  *out is NULL on error.
@@ -151,6 +162,7 @@ typedef struct {
 /* Read (get) or replace (set) the SVD controls of a handle.  set validates every field
  * (EINVAL, nothing changed).  Both return EINVAL on a NULL pointer. */
 int ptebd_get_svd_params(ptebd_mps_t h, ptebd_svd_params* out);
+/* Replace the controls (validated first; on EINVAL nothing changes). */
 int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* params);
 
 /*
@@ -168,7 +180,11 @@ int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* params);
  *   flags        0 or an OR of PTEBD_FLAG_NO_STABILIZE and one of PTEBD_FLAG_RELATIVE_EPS,
  *                PTEBD_FLAG_COMPLEMENT_EPS (both eps flags: EINVAL);
  *   stats        optional per-layer statistics (see ptebd_layer_stats).
- * The gates of one state must act on disjoint sites (else EOVERLAP).  The call enqueues
+ * The gates of one state must act on disjoint sites (else EOVERLAP).  As in Algorithm 1,
+ * the layer counts as compressed for a state when some gate of that state had r > chi_max
+ * ("if chi~ > chi"); only then are that state's new Schmidt values multiplied by nu_i and
+ * the PtSU steps run (IPMC, Sec. III.E).  On a layer that needed no compression every
+ * nu_i is 1 and Lambda[q+1] is the kept singular values as they are.  The call enqueues
  * the layer on the handle's stream and returns after it has completed (the new bond
  * dimensions are read back to size the next layer).
  * Errors: EINVAL, EOVERLAP, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV.
@@ -206,29 +222,48 @@ int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out);
  * ENONFINITE (a conditional probability vanished: the state was not canonical). */
 int ptebd_sample(ptebd_mps_t h, int s, int n_samples, const double* uniforms, uint8_t* bits);
 
-/* Run g PtSU steps on state s (tSU on all pairs (0,1),(2,3),..., then (1,2),(3,4),...;
- * each tSU is the TEBD procedure with the identity gate skipped, cutoff only, nu = 1). */
+/* Run g parallel trivial-simple-update (PtSU) steps on state s, the canonical-form recovery
+ * of Sec. III.D (Theorem 4: N/2 steps restore the exact canonical form for even N): each step
+ * is a tSU on all pairs (0,1),(2,3),..., then on (1,2),(3,4),...; a tSU is the TEBD procedure
+ * of Sec. II.C with the identity gate skipped (the shortcut noted in Sec. III.D), cutoff only
+ * (no chi bound), nu = 1.  It leaves the state unchanged up to rounding and the cutoff.
+ * steps >= 0, cutoff in [0, 1).  Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED;
+ * warning WNOCONV. */
 int ptebd_ptsu(ptebd_mps_t h, int s, int steps, double cutoff);
 
-/* Exact sqrt(<Psi|Psi>) of state s in FP64 by a left-to-right transfer sweep. */
+/* Exact norm n = sqrt(<Psi|Psi>) of state s (the quantity whose decay Sec. III.C.1 studies)
+ * in FP64, by the left-to-right transfer sweep of the quantum-map recursion Eq. (recu) with
+ * no projector inserted.  The cost is sequential in N (O(N chi^3)).  out: one double.
+ * Errors: EINVAL (bad handle or state, NULL out), ENOMEM, EDEVICE. */
 int ptebd_norm(ptebd_mps_t h, int s, double* out);
 
-/* Exact <Psi_a|Psi_b> in FP64 (states may differ in precision and bond dimensions but
- * must have the same number of sites). */
+/* Exact overlap <Psi_a|Psi_b> in FP64, the quantity in the fidelities of Eq. (F_2) and
+ * Eq. (F), by a transfer sweep over both chains.  The states may live in different handles
+ * (of the same device), differ in precision and bond dimensions, but must have the same
+ * number of sites.  Everything runs on ha's stream after hb's pending work has completed.
+ * re, im: one double each.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ptebd_overlap(ptebd_mps_t ha, int sa, ptebd_mps_t hb, int sb, double* re, double* im);
 
-/* <Z_q> / <Psi|Psi> for every site q of state s (out: N doubles), from FP64 left and
- * right environments. */
+/* <Z_q> / <Psi|Psi> for every site q of state s (out: N doubles), from FP64 left and right
+ * environments (the L and R partial contractions of Eqs. (llid)-(rrid), without assuming
+ * they are identities): the "measurements" step of Algorithm 1, exact for any state, so it
+ * needs no Canonicalize first.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ptebd_expect_z(ptebd_mps_t h, int s, double* out);
 
 /* Distance to the canonical form, Eq. (dist_to_cano), of state s scaled to norm 1
  * (every inner Lambda multiplied by n^(-1/(N-1))). */
 int ptebd_canon_distance(ptebd_mps_t h, int s, double* out);
 
-/* n*_upper = prod of every nu_i applied to state s since create/import (Theorem 3). */
+/* n*_upper = prod of every nu_i applied to state s since create/import (Eq. (n_up) of
+ * Theorem 3).  out: one double.  Errors: EINVAL. */
 int ptebd_norm_estimate(ptebd_mps_t h, int s, double* out);
 
-/* Fidelity estimate prod over all truncations of (1 - eps_i) since create/import. */
+/* Fidelity estimate: the product over every applied truncation since create/import of
+ * (1 - eps_i), eps_i the local error of Theorem 1 (on a normalized canonical input the
+ * fidelity of one bond's truncation is 1 - eps_i).  The paper defines no fidelity estimator
+ * for a whole pTEBD run; this is the product of the per-bond values.  Under the complement
+ * reading eps_i also absorbs the deviation of a non-normalized bond from unit weight, so the
+ * product is then a diagnostic, not a fidelity.  out: one double.  Errors: EINVAL. */
 int ptebd_fidelity_estimate(ptebd_mps_t h, int s, double* out);
 
 /* Bond dimensions chi_0..chi_N of state s into out[0..N] (cap >= N+1). */
@@ -307,7 +342,11 @@ typedef struct {
   double bytes;      /* algorithmic HBM bytes of those launches */
 } ptebd_kernel_stats;
 
+/* enable != 0: start timing the handle's kernels (every class reset to zero); 0: stop.
+ * Waits for the handle's stream first.  Errors: EINVAL (bad handle), EDEVICE. */
 int ptebd_set_profiling(ptebd_mps_t h, int enable);
+/* The accumulated timing of kernel class `kind` (PTEBD_KERNEL_*) since profiling was enabled;
+ * waits for the handle's stream first.  Errors: EINVAL (bad handle, class or NULL out). */
 int ptebd_get_kernel_stats(ptebd_mps_t h, int kind, ptebd_kernel_stats* out);
 
 #ifdef __cplusplus

@@ -103,7 +103,8 @@ EPS_READINGS = ("literal", "relative", "complement")
 
 
 def bond_update(mps: VidalMPS, q: int, gate, chi_max: int | None, cutoff: float,
-                stabilize: bool = True, eps_reading: str = "literal") -> dict:
+                stabilize: bool = True, eps_reading: str = "literal",
+                apply_nu: bool = True) -> dict:
     """One TEBD procedure at bond q+1 with truncation and norm stabilization.
 
     Steps (Sec. II.C; Sec. III.B; Theorem 1; Eq. (lren)):
@@ -116,7 +117,8 @@ def bond_update(mps: VidalMPS, q: int, gate, chi_max: int | None, cutoff: float,
          ``eps_reading`` picks one: "literal" the discarded sigma^2; "relative" the discarded
          sigma^2 divided by sum sigma^2; "complement" 1 - sum of the kept sigma^2, which
          makes nu rescale the kept values to unit norm;
-      4. nu = (1 - eps)^(-1/2) when stabilizing, else 1;  Lambda[q+1] = nu * S[:k];
+      4. nu = (1 - eps)^(-1/2) when stabilizing, else 1;  Lambda[q+1] = nu * S[:k]
+         (with ``apply_nu`` False, Lambda[q+1] = S[:k] and the caller decides on nu);
       5. Gamma[q] = X[:, :k] / Lambda[q],  Gamma[q+1] = Y^dagger[:k] / Lambda[q+2].
     """
     ll, lr = mps.lam[q], mps.lam[q + 2]
@@ -140,7 +142,7 @@ def bond_update(mps: VidalMPS, q: int, gate, chi_max: int | None, cutoff: float,
         nu = (1.0 - eps) ** -0.5
     else:
         nu = 1.0
-    mps.lam[q + 1] = nu * s[:k]
+    mps.lam[q + 1] = nu * s[:k] if apply_nu else s[:k].copy()
     mps.gam[q] = x[:, :k].reshape(len(ll), 2, k) / ll[:, None, None]
     mps.gam[q + 1] = yh[:k].reshape(k, 2, len(lr)) / lr[None, None, :]
     return {"q": q, "k": k, "r": r, "eps": eps, "nu": nu, "sigma": s}
@@ -174,24 +176,34 @@ def ptsu_step(mps: VidalMPS, cutoff: float) -> None:
 
 def apply_layer(mps: VidalMPS, bonds, gates, chi_max: int, cutoff: float = 1e-12,
                 ptsu_steps: int = 0, stabilize: bool = True, eps_reading: str = "literal"):
-    """One pTEBD step (Algorithm 1): parallel TEBD on every gate of the layer with the
-    per-bond truncation to chi_max and norm stabilization; if any gate's rank exceeded
-    chi_max the layer was compressed and ``ptsu_steps`` PtSU steps follow (IPMC, Sec. III.E).
+    """One pTEBD step (Algorithm 1): the TEBD procedure on every gate of the layer, each bond
+    cut to chi_max.  If some gate's rank exceeded chi_max ("if chi~ > chi") the layer is
+    compressed by IPMC (Sec. III.E): the truncated bonds' Schmidt values are multiplied by
+    their nu_i (norm stabilization, Sec. III.C.2) and ``ptsu_steps`` PtSU steps follow.
+    Otherwise the bonds keep their singular values as they are and nu_i = 1 (the "else"
+    branch of Algorithm 1; the cutoff still drops values below cutoff * sigma_1).
 
     Gates touch disjoint sites and read only Lambda[q], Lambda[q+2], which no gate of the same
     layer writes, so the order of the gates does not matter; they are processed in ascending q.
-    Returns (list of per-gate stats in ascending-q order, triggered flag).
+    Returns (list of per-gate stats in ascending-q order, triggered flag); each gate's "nu"
+    is the factor actually applied.
     """
     bonds = [int(q) for q in bonds]
     _check_disjoint(mps.n_sites, bonds)
     order = np.argsort(bonds, kind="stable")
     stats = [None] * len(bonds)
     for idx in order:
-        st = bond_update(mps, bonds[idx], gates[idx], chi_max, cutoff, stabilize, eps_reading)
+        stats[idx] = bond_update(mps, bonds[idx], gates[idx], chi_max, cutoff, stabilize,
+                                 eps_reading, apply_nu=False)
+    triggered = any(st["r"] > chi_max for st in stats)
+    for idx, st in enumerate(stats):
+        if triggered:
+            q = bonds[idx]
+            mps.lam[q + 1] = st["nu"] * mps.lam[q + 1]
+        else:
+            st["nu"] = 1.0
         mps.prod_nu *= st["nu"]
         mps.prod_one_minus_eps *= (1.0 - st["eps"])
-        stats[idx] = st
-    triggered = any(st["r"] > chi_max for st in stats)
     if triggered:
         for _ in range(int(ptsu_steps)):
             ptsu_step(mps, cutoff)

@@ -670,11 +670,25 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
     PT_HIP(hipMemcpy(c2, (char*)h->outbuf.p + L.counters2, sizeof(c2), hipMemcpyDeviceToHost));
     hc[2] |= c2[2];
   }
+  // Algorithm 1 compresses a state's layer (nu, then PtSU) only when some of its gates had
+  // r > chi; the finalize kernels left Lambda[q+1] = sigma[:k], and nu multiplies it for the
+  // gates of such states only.
+  std::vector<char> trig(h->st.size(), 0);
+  if (stabilize)
+    for (int i = 0; i < n; ++i)
+      if (items[i].chi > 0 && hr[i] > items[i].chi) trig[items[i].s] = 1;
+  int32_t* happ = (int32_t*)h->h_gates.p;  // the gates' staging is free again
+  for (int i = 0; i < n; ++i) happ[i] = trig[items[i].s] ? 1 : 0;
+  if (stabilize) {
+    PT_HIP(hipMemcpyAsync(h->gates.p, happ, sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+    ptebd::launch_apply_nu(d_desc, n, (const int32_t*)h->gates.p, lo, stream);
+    PT_HIP(hipGetLastError());
+  }
   for (int i = 0; i < n; ++i) {
     res->k[i] = hk[i];
     res->r[i] = hr[i];
     res->eps[i] = he[i];
-    res->nu[i] = hn[i];
+    res->nu[i] = (stabilize && happ[i]) ? hn[i] : 1.0;
     res->sweeps[i] = hs[i];
     res->max_sweeps = std::max(res->max_sweeps, hs[i]);
     h->st[items[i].s].dims[items[i].q + 1] = hk[i];
@@ -793,16 +807,18 @@ int get_qscratch(ptebd_mps* h, int cap, QScratch* q, size_t n_red) {
   return PTEBD_OK;
 }
 
+// A_s = diag(lam_left) Gamma[q]_s diag(lam_right) of state s of h, in FP64, into out, on
+// `stream` (the stream of the query that owns `out`, which may belong to another handle).
 void site_a(const ptebd_mps* h, int s, int q, const double* lam_left, const double* lam_right,
-            double sl, double sr, cplx<double>* out) {
+            double sl, double sr, cplx<double>* out, hipStream_t stream) {
   const StateInfo& si = h->st[s];
   const int cl = si.dims[q], cm = si.dims[q + 1];
   if (h->precision == PTEBD_FP64)
     ptebd::launch_site_a<double>(h->gamma_slot(s, q), lam_left, lam_right, cl, cm, sl, sr, out,
-                                 h->stream);
+                                 stream);
   else
     ptebd::launch_site_a<float>(h->gamma_slot(s, q), lam_left, lam_right, cl, cm, sl, sr, out,
-                                h->stream);
+                                stream);
 }
 
 }  // namespace
@@ -820,6 +836,8 @@ int ptebd_mps_create(int n_states, const int32_t* n_sites, const int32_t* chi_ca
   *out = nullptr;
   if (n_states < 1 || !n_sites || !chi_cap) return fail(PTEBD_EINVAL, "need n_states >= 1 and arrays");
   if (d != 2) return fail(PTEBD_EINVAL, "local dimension d must be 2");
+  if (precision == PTEBD_BF16X3)
+    return fail(PTEBD_EINVAL, "PTEBD_BF16X3 is not built in this library (use PTEBD_FP32)");
   if (precision != PTEBD_FP64 && precision != PTEBD_FP32)
     return fail(PTEBD_EINVAL, "precision must be PTEBD_FP64 or PTEBD_FP32");
   for (int s = 0; s < n_states; ++s) {
@@ -1212,7 +1230,8 @@ int ptebd_overlap(ptebd_mps_t ha, int sa, ptebd_mps_t hb, int sb, double* re, do
   if (A.n != B.n) return fail(PTEBD_EINVAL, "states differ in the number of sites");
   if (ha->device != hb->device) return fail(PTEBD_EINVAL, "handles live on different devices");
   PT_CHECK(set_device(ha));
-  // order hb's work after its pending work, then run everything on ha's stream
+  // hb's pending work has completed; from here on every kernel, hb's site tensors included,
+  // runs on ha's stream, which orders them against the scratch buffers they share
   PT_HIP(hipStreamSynchronize(hb->stream));
   const int cap = std::max(A.cap, B.cap);
   QScratch q;
@@ -1223,8 +1242,8 @@ int ptebd_overlap(ptebd_mps_t ha, int sa, ptebd_mps_t hb, int sb, double* re, do
   for (int site = 0; site < A.n; ++site) {
     const int cla = A.dims[site], cma = A.dims[site + 1];
     const int clb = B.dims[site], cmb = B.dims[site + 1];
-    site_a(ha, sa, site, ha->lam_slot(sa, site), nullptr, 1.0, 1.0, q.a);
-    site_a(hb, sb, site, hb->lam_slot(sb, site), nullptr, 1.0, 1.0, q.b);
+    site_a(ha, sa, site, ha->lam_slot(sa, site), nullptr, 1.0, 1.0, q.a, stream);
+    site_a(hb, sb, site, hb->lam_slot(sb, site), nullptr, 1.0, 1.0, q.b, stream);
     // F_s = E B_s : (cla x clb)(clb x cmb)
     for (int s = 0; s < 2; ++s)
       ptebd::launch_zgemm('N', 'N', cla, cmb, clb, 1.0, q.e, cla, q.b + (size_t)s * clb * cmb, clb,
@@ -1270,7 +1289,7 @@ int ptebd_expect_z(ptebd_mps_t h, int s, double* out) {
   ptebd::launch_set_identity_scalar(renv + (size_t)n * blk, 1.0, stream);
   for (int site = n - 1; site >= 0; --site) {
     const int cl = si.dims[site], cm = si.dims[site + 1];
-    site_a(h, s, site, h->lam_slot(s, site), nullptr, 1.0, 1.0, q.a);
+    site_a(h, s, site, h->lam_slot(s, site), nullptr, 1.0, 1.0, q.a, stream);
     for (int p = 0; p < 2; ++p)
       ptebd::launch_zgemm('N', 'N', cl, cm, cm, 1.0, q.a + (size_t)p * cl * cm, cl,
                           renv + (size_t)(site + 1) * blk, cm, 0.0, q.f + p * blk, cl, stream);
@@ -1282,7 +1301,7 @@ int ptebd_expect_z(ptebd_mps_t h, int s, double* out) {
   ptebd::launch_set_identity_scalar(q.e, 1.0, stream);
   for (int site = 0; site < n; ++site) {
     const int cl = si.dims[site], cm = si.dims[site + 1];
-    site_a(h, s, site, h->lam_slot(s, site), nullptr, 1.0, 1.0, q.a);
+    site_a(h, s, site, h->lam_slot(s, site), nullptr, 1.0, 1.0, q.a, stream);
     for (int p = 0; p < 2; ++p) {
       // F_p = L A_p (cl x cm)
       ptebd::launch_zgemm('N', 'N', cl, cm, cl, 1.0, q.e, cl, q.a + (size_t)p * cl * cm, cl, 0.0,
@@ -1327,8 +1346,8 @@ int ptebd_canon_distance(ptebd_mps_t h, int s, double* out) {
     const double sl = (site >= 1) ? scale : 1.0;
     const double sr = (site + 1 <= n - 1) ? scale : 1.0;
     // A = Lambda[q] Gamma[q] and B = Gamma[q] Lambda[q+1] with the inner Lambdas scaled
-    site_a(h, s, site, h->lam_slot(s, site), nullptr, sl, 1.0, q.a);
-    site_a(h, s, site, nullptr, h->lam_slot(s, site + 1), 1.0, sr, q.b);
+    site_a(h, s, site, h->lam_slot(s, site), nullptr, sl, 1.0, q.a, stream);
+    site_a(h, s, site, nullptr, h->lam_slot(s, site + 1), 1.0, sr, q.b, stream);
     for (int p = 0; p < 2; ++p)
       ptebd::launch_zgemm('C', 'N', cm, cm, cl, 1.0, q.a + (size_t)p * cl * cm, cl,
                           q.a + (size_t)p * cl * cm, cl, p == 0 ? 0.0 : 1.0, q.e, cm, stream);
@@ -1698,6 +1717,8 @@ int svd_batched_t(int precision, int batch, int m, int n, const double* a, doubl
 extern "C" int ptebd_svd_batched(int precision, int batch, int m, int n, const double* a,
                                  double* s, double* u, double* vh, int32_t* sweeps,
                                  int max_sweeps, double tol_factor, void* hip_stream) {
+  if (precision == PTEBD_BF16X3)
+    return fail(PTEBD_EINVAL, "PTEBD_BF16X3 is not built in this library (use PTEBD_FP32)");
   if (precision != PTEBD_FP64 && precision != PTEBD_FP32) return fail(PTEBD_EINVAL, "bad precision");
   if (batch < 1 || m < 1 || n < 1 || std::min(m, n) > 1024 || batch > 65535)
     return fail(PTEBD_EINVAL, "bad sizes (batch in [1, 65535], min(m, n) <= 1024)");

@@ -780,7 +780,9 @@ __global__ void sweep_check_kernel(const GateDesc* __restrict__ descs, int n_gat
 // ---------------------------------------------------------------- finalize
 // sigma_j = |W_j| (FP64), descending sort with the column permutation, r = #{sigma >
 // cutoff sigma_1}, k = min(chi_max, r), eps = sum_{j >= k} sigma_j^2, nu = (1-eps)^(-1/2),
-// Lambda[q+1] = nu sigma[:k].
+// Lambda[q+1] = sigma[:k].  Whether nu multiplies Lambda[q+1] depends on the whole layer
+// (Algorithm 1 compresses only when some bond exceeded chi), so apply_nu_kernel does that
+// once every gate of the batch has been finalized.
 template <class T>
 __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restrict__ descs,
                                                        double cutoff, LayerOut out) {
@@ -867,7 +869,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
     const double s = sqrt(fmax(key[j], 0.0));
     out.sig[(size_t)g * out.cmax + j] = s;
     out.perm[(size_t)g * out.cmax + j] = idx[j];
-    if (lam_m != nullptr && j < k) lam_m[j] = nu * s;
+    if (lam_m != nullptr && j < k) lam_m[j] = s;
   }
   if (tid == 0) {
     out.k[g] = k;
@@ -879,6 +881,23 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
     if (!isfinite(s1) || !isfinite(eps) || !isfinite(nu)) err |= 2;
     if (err) atomicOr(&out.counters[2], err);
   }
+}
+
+// Norm stabilization of a compressed layer (Sec. III.C.2, Eq. (lren)): Lambda[q+1] <- nu
+// Lambda[q+1] for the gates whose state's layer was compressed (apply[g] != 0); the others
+// keep their singular values and report nu = 1.
+__global__ __launch_bounds__(256) void apply_nu_kernel(const GateDesc* __restrict__ descs,
+                                                       const int32_t* __restrict__ apply,
+                                                       LayerOut out) {
+  const int g = blockIdx.x;
+  const gptr<double> lam_m = as_global(descs[g].lam_m);
+  if (!apply[g]) {
+    if (threadIdx.x == 0) out.nu[g] = 1.0;
+    return;
+  }
+  const double nu = out.nu[g];
+  const int k = out.k[g];
+  for (int j = threadIdx.x; j < k; j += blockDim.x) lam_m[j] = nu * lam_m[j];
 }
 
 // ---------------------------------------------------------------- write-back
@@ -998,6 +1017,12 @@ void launch_finalize(const GateDesc* d_desc, int n_gates, double cutoff, const L
   if (n_gates <= 0) return;
   hipLaunchKernelGGL(finalize_kernel<T>, dim3(n_gates), dim3(256), 0, stream, d_desc, cutoff,
                      out);
+}
+
+void launch_apply_nu(const GateDesc* d_desc, int n_gates, const int32_t* d_apply,
+                     const LayerOut& out, hipStream_t stream) {
+  if (n_gates <= 0) return;
+  hipLaunchKernelGGL(apply_nu_kernel, dim3(n_gates), dim3(256), 0, stream, d_desc, d_apply, out);
 }
 
 template <class T>

@@ -26,6 +26,7 @@ WNOCONV = 1
 
 FP64 = 0
 FP32 = 1
+BF16X3 = 2  # declared by the header, not built: the library rejects it with EINVAL
 FLAG_NO_STABILIZE = 1
 FLAG_RELATIVE_EPS = 2
 FLAG_COMPLEMENT_EPS = 4

@@ -50,6 +50,7 @@ def _create(n_states, n_sites, caps, d=2, precision=0):
     (1, [10], [0], 2, 0),       # chi_cap < 1
     (1, [10], [1024], 2, 0),    # chi_cap > 512
     (1, [10], [32], 2, 7),      # unknown precision
+    (1, [10], [32], 2, 2),      # PTEBD_BF16X3: declared, not built
 ])
 def test_create_rejects_bad_arguments_before_device_work(args):
     code, h = _create(*args)
@@ -74,6 +75,9 @@ def test_svd_batched_rejects_bad_arguments():
     ps = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert lib.ptebd_svd_batched(0, 0, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
     assert lib.ptebd_svd_batched(5, 1, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
+    assert lib.ptebd_svd_batched(ptebd.BF16X3, 1, 2, 2, p, ps, None, None, None, 30, 4.0,
+                                 None) == ptebd.EINVAL
+    assert "not built" in lib.ptebd_last_error().decode()
     a[0] = np.nan
     assert lib.ptebd_svd_batched(0, 1, 2, 2, p, ps, None, None, None, 30, 4.0, None) == ptebd.EINVAL
 
@@ -86,3 +90,17 @@ def test_header_constants_match_binding():
     assert int(defs["PTEBD_FLAG_RELATIVE_EPS"]) == ptebd.FLAG_RELATIVE_EPS
     assert int(defs["PTEBD_FLAG_COMPLEMENT_EPS"]) == ptebd.FLAG_COMPLEMENT_EPS
     assert float(defs["PTEBD_FP32_CUTOFF_FLOOR"]) == ptebd.FP32_CUTOFF_FLOOR == 2.0 ** -19
+    assert int(defs["PTEBD_FP64"]) == ptebd.FP64 and int(defs["PTEBD_FP32"]) == ptebd.FP32
+    assert int(defs["PTEBD_BF16X3"]) == ptebd.BF16X3
+
+
+def test_every_declaration_cites_or_documents():
+    """Every entry point in the header carries a comment block of its own (the passage it
+    follows, or what it is for), placed right above its declaration."""
+    src = open(os.path.join(ROOT, "include", "ptebd.h")).read()
+    for name in _declared_functions():
+        idx = re.search(r"^[a-z][a-z_ *]*\b" + name + r"\(", src, flags=re.M).start()
+        head = src[:idx]
+        # the text between the previous declaration's end and this one holds a comment
+        prev = max(head.rfind(";"), head.rfind("{"))
+        assert "*/" in head[prev:], name

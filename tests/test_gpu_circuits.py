@@ -261,7 +261,7 @@ def test_pqc_2d_truncation_values_match_oracle(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_norm_stabilization_ablation_on_gpu(precision):
-    """Sec. V.B: RQC-1D, N=21, chi_max=4, 160 layers.  Without nu the norm decays monotonically
+    """Sec. IV.B, numerical stability: RQC-1D, N=21, chi_max=4, 160 layers.  Without nu the norm decays monotonically
     to below 1e-5; with nu under the complement reading it stays within [0.8, 1.25].  The GPU
     norms follow the oracle's layer by layer."""
     from paper_2312_02667_amd import circuits

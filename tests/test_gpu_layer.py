@@ -29,7 +29,8 @@ def test_small_exact_circuit(precision, seed):
         assert not st["triggered"]
         assert m.bond_dims() == ref.bond_dims()
         assert lambda_diff(to_oracle(m), ref) <= lam_tol
-        assert np.all(st["nu"] == 1.0) or precision == "fp32"
+        # nothing is compressed, so no nu is applied (Algorithm 1's "else" branch)
+        assert np.all(st["nu"] == 1.0)
     f_tol = 1e-12 if precision == "fp64" else 1e-9
     dense = po.to_dense(to_oracle(m))
     assert 1 - sv.fidelity(psi, dense) <= f_tol
@@ -217,3 +218,64 @@ def test_svd_params_round_trip_and_validation():
     d = ptebd.MPS(6, 8, "fp64")
     assert d.svd_params()["inner_sweeps"] == 1 and d.svd_params()["inner_repeat"] == 0.0
     d.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("reading", ["literal", "complement"])
+def test_nu_only_on_compressed_layers_matches_oracle(precision, reading):
+    """A canonical state with two bonds scaled (0.9, 1.3), gates at q = 3 and q = 0: with
+    chi_max = 16 nothing is compressed and both bonds keep their singular values (nu = 1); with
+    chi_max = 3 the layer is compressed and both bonds, the untruncated one too, are
+    multiplied by their nu.  Lambda, eps and nu against the oracle."""
+    n = 8
+    g, l = inputs.random_vidal_state(n, 8, seed=5)
+    raw = po.VidalMPS(g, l)
+    can, _ = po.canonicalize(raw)
+    po.scale_norm(can, 1.0 / po.norm(can))
+    can.lam[1] = 0.9 * can.lam[1]
+    can.lam[4] = 1.3 * can.lam[4]
+    rng = np.random.default_rng(50)
+    gates = [inputs.haar_unitary(rng), inputs.haar_unitary(rng)]
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    for chi_max, want_trig in ((16, False), (3, True)):
+        say(f"nu trigger {precision} {reading} chi_max={chi_max}")
+        ref = can.copy()
+        stats, trig = po.apply_layer(ref, [3, 0], gates, chi_max=chi_max,
+                                     cutoff=oracle_cutoff(1e-12, precision), eps_reading=reading)
+        assert trig == want_trig
+        m = ptebd.MPS(n, 16, precision)
+        m.import_state(can.gam, can.lam)
+        st = m.apply_layer([3, 0], gates, chi_max=chi_max, cutoff=1e-12, eps_reading=reading)
+        assert st["triggered"] == want_trig
+        assert m.bond_dims() == ref.bond_dims()
+        assert lambda_diff(to_oracle(m), ref) <= tol
+        assert np.max(np.abs(st["nu"] - np.array([x["nu"] for x in stats]))) <= tol
+        assert np.max(np.abs(st["eps"] - np.array([x["eps"] for x in stats]))) <= tol
+        if not want_trig:
+            assert np.all(st["nu"] == 1.0)
+        m.close()
+
+
+def test_overlap_of_handles_on_different_streams():
+    """Two handles on two different HIP streams: the overlap query runs every kernel on the
+    first handle's stream (the second's site tensors are staged in the first's scratch), so
+    the result matches the oracle."""
+    import torch
+
+    n = 12
+    ga, la = inputs.random_vidal_state(n, 16, seed=31)
+    gb, lb = inputs.random_vidal_state(n, 16, seed=32)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ma = ptebd.MPS(n, 16, "fp64", stream=sa.cuda_stream)
+    mb = ptebd.MPS(n, 16, "fp32", stream=sb.cuda_stream)
+    ma.import_state(ga, la)
+    mb.import_state(gb, lb)
+    a, b = po.VidalMPS(ga, la), to_oracle(mb)
+    ref = po.overlap(a, b)
+    for _ in range(3):
+        ov = ma.overlap(mb)
+        assert abs(ov - ref) <= 1e-12 * po.norm(a) * po.norm(b)
+        ov2 = mb.overlap(ma)
+        assert abs(ov2 - np.conj(ref)) <= 1e-12 * po.norm(a) * po.norm(b)
+    ma.close()
+    mb.close()

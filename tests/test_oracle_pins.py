@@ -364,8 +364,61 @@ def test_eps_readings_on_a_scaled_canonical_state(scale):
         po.apply_layer(mps.copy(), [3], [u], chi_max=3, eps_reading="other")
 
 
+def _dense_schmidt(psi, n, cut):
+    """Schmidt values of a state vector across the cut after site ``cut - 1``."""
+    return np.linalg.svd(np.asarray(psi).reshape(2 ** cut, 2 ** (n - cut)), compute_uv=False)
+
+
+@pytest.mark.parametrize("reading", ["literal", "complement"])
+def test_nu_only_on_compressed_layers(reading):
+    """Algorithm 1 compresses (IPMC: projector truncation, then nu, then PtSU) only when the
+    layer's new bond dimension exceeds chi ("if chi~ > chi"); otherwise the TEBD result is kept
+    as it is.  A canonical state with bond 1 scaled by c1 = 0.9 and bond 4 by c4 = 1.3 is the
+    unit-norm canonical state times c1 c4, and after gates at q = 0 and q = 3 the local
+    two-site wavefunctions carry the singular values c1 s1 and c4 s4, where c1 c4 s_i are the
+    dense state's Schmidt values across the cut (unit-norm s_i).  So:
+      * untriggered (chi_max = 16): Lambda[1] = c1 s1 and Lambda[4] = c4 s4, unscaled, nu = 1;
+      * triggered (chi_max = 3, only bond 4 truncated): Lambda[4] = nu4 * the top 3 of c4 s4,
+        and the untruncated bond 1 is multiplied by its own nu1 as well: under the complement
+        reading nu1 = 1 / c1, under the literal one nu1 = 1 (nothing discarded)."""
+    n, c1, c4 = 8, 0.9, 1.3
+    _, mps = _canonical_random_state(n, 23)
+    u = inputs.haar_unitary(np.random.default_rng(230))
+    v = inputs.haar_unitary(np.random.default_rng(231))
+    base = mps.copy()
+    base.lam[1] = c1 * base.lam[1]
+    base.lam[4] = c4 * base.lam[4]
+    after = sv.apply_gate(sv.apply_gate(po.to_dense(base), n, 3, u), n, 0, v)
+    loc = {4: _dense_schmidt(after, n, 4) / c1, 1: _dense_schmidt(after, n, 1) / c4}
+    m = base.copy()
+    st, trig = po.apply_layer(m, [3, 0], [u, v], chi_max=16, eps_reading=reading)
+    assert not trig
+    assert [x["nu"] for x in st] == [1.0, 1.0]
+    for bond, scale in ((4, c4), (1, c1)):
+        k = len(m.lam[bond])
+        assert np.max(np.abs(m.lam[bond] - loc[bond][:k])) < 1e-13
+        assert abs(np.sum(m.lam[bond] ** 2) - scale ** 2) < 1e-12
+    m = base.copy()
+    st, trig = po.apply_layer(m, [3, 0], [u, v], chi_max=3, eps_reading=reading)
+    assert trig and st[0]["r"] > 3 and st[1]["r"] <= 3
+    for idx, bond in enumerate((4, 1)):
+        sref = loc[bond]
+        k = len(m.lam[bond])
+        kept2 = float(np.sum(sref[:k] ** 2))
+        eps = float(np.sum(sref[k:] ** 2)) if reading == "literal" else 1.0 - kept2
+        assert abs(st[idx]["eps"] - eps) < 1e-12
+        nu = (1.0 - eps) ** -0.5
+        assert abs(st[idx]["nu"] - nu) < 1e-12
+        assert np.max(np.abs(m.lam[bond] - nu * sref[:k])) < 1e-12
+    if reading == "complement":
+        assert abs(st[1]["nu"] - 1.0 / c1) < 1e-12
+        assert abs(np.sum(m.lam[4] ** 2) - 1.0) < 1e-12
+    else:
+        assert abs(st[1]["nu"] - 1.0) < 1e-12
+
+
 def test_norm_stabilization_ablation_rqc_1d():
-    """Sec. V.B (the norm-vs-depth figure): without nu the norm of a truncated RQC-1D decays
+    """Sec. IV.B, numerical stability (the norm-vs-depth figure): without nu the norm of a truncated RQC-1D decays
     monotonically and exponentially; with nu under the complement reading it stays near 1.
     Under the literal reading the stabilized norm leaves that band within the same circuit
     (norm 1 is a repelling fixed point, see the scaled-state pin above)."""
