@@ -11,7 +11,8 @@ saturated layer.  The steps walk through layers 10..20 in order; when ``--warmup
 ``--steps`` exceed 11, the walk starts again at layer 10 from a checkpoint of the state after
 layer 9 (exported once, imported into the same handle before each further pass), so the
 circuit depth never exceeds 20.  The first ``--warmup`` steps are untimed; each timed step is
-bracketed by device synchronizations, and the checkpoint imports fall between steps.
+bracketed by device synchronizations (of the HIP runtime the library runs on; torch is not
+used on the GPU path), and the checkpoint imports fall between steps.
 
 The headline path is the mixed-precision one (FP32 contractions and Jacobi column updates,
 FP64 rotation angles, singular values, eps, nu, Lambda and Lambda^{-1} divisions).  The FP64
@@ -130,12 +131,12 @@ class Path:
         self.m.import_state(g, l)
 
     def timed_layer(self, idx, bonds, gates):
-        import torch
+        from paper_2312_02667_amd import ptebd
 
-        torch.cuda.synchronize()
+        ptebd.device_synchronize()
         t0 = time.perf_counter()
         st = self.layer(bonds, gates)
-        torch.cuda.synchronize()
+        ptebd.device_synchronize()
         dt = time.perf_counter() - t0
         self.step_s.append(dt)
         self.layers.append({"layer": idx + 1, "wall_ms": 1e3 * dt, "device_ms": st["device_ms"],
@@ -323,15 +324,13 @@ def measure_f1(precision: str, n_sites: int, chi: int, depth: int, n_samples: in
     """The measurement step after the last layer (Algorithm 1): canonicalize a truncated
     Haar-circuit state, then draw n_samples bit strings by perfect sampling.  Returns wall
     times and the sampling kernel's achieved rate (algorithmic flops / event time)."""
-    import torch
-
     from paper_2312_02667_amd import inputs, ptebd
 
     layers = inputs.brickwork_circuit(n_sites, depth, seed)
     m = ptebd.MPS(n_sites, chi, precision)
     for bonds, gates in layers:
         m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12, eps_reading=EPS_READING)
-    torch.cuda.synchronize()
+    ptebd.device_synchronize()
     t0 = time.perf_counter()
     nrm = m.canonicalize(cutoff=1e-12)
     t_can = time.perf_counter() - t0
@@ -379,14 +378,15 @@ def main(argv=None):
         cpu = cpu_baseline(args.chi, args.cpu_seconds)
         log(f"cpu baseline: {cpu['value']:.2f} bond updates/s ({cpu['mode']})")
 
-    import torch
+    from paper_2312_02667_amd import inputs, ptebd
 
-    from paper_2312_02667_amd import inputs
-
-    torch.cuda.init()
-    stream = torch.cuda.current_stream().cuda_stream
+    ptebd.set_device(0)
+    stream = ptebd.default_stream()
     if args.copy_calibration > 0:
-        # an elementwise kernel that reads MIB MiB and writes MIB MiB (dst = 2 * src)
+        # an elementwise kernel that reads MIB MiB and writes MIB MiB (dst = 2 * src); torch
+        # runs it on its own HIP runtime, which is all a hardware counter calibration needs
+        import torch
+
         n_el = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n_el, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -1,8 +1,14 @@
 """ctypes binding of libptebd (argument marshalling only; every step runs in the library).
 
 The library must have been built (``paper_2312_02667_amd.build.build()``); loading fails
-loudly otherwise.  PyTorch, when present, only supplies the HIP stream
-(``torch.cuda.current_stream().cuda_stream``).
+loudly otherwise.
+
+HIP runtime: libptebd links the system ROCm HIP runtime (``libamdhip64.so.7``).  The PyTorch
+wheel of this image bundles a HIP runtime of its own, a separate instance in the same
+process, so torch's stream handles and device pointers mean nothing to the library and the
+binding never passes them.  The library allocates its own device memory; streams, when a
+caller wants one other than the null stream, come from the library's runtime (``Stream``),
+and ``device_synchronize`` waits for that runtime's work.
 """
 
 from __future__ import annotations
@@ -139,16 +145,63 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
+_HIP = None
+
+
+def hip():
+    """The HIP runtime instance libptebd uses (loaded by the library itself; same soname)."""
+    global _HIP
+    if _HIP is None:
+        lib()
+        h = ctypes.CDLL("libamdhip64.so.7")
+        h.hipDeviceSynchronize.restype = ctypes.c_int
+        h.hipSetDevice.argtypes = [ctypes.c_int]
+        h.hipSetDevice.restype = ctypes.c_int
+        h.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        h.hipStreamCreateWithFlags.restype = ctypes.c_int
+        h.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+        h.hipStreamDestroy.restype = ctypes.c_int
+        h.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+        h.hipStreamSynchronize.restype = ctypes.c_int
+        _HIP = h
+    return _HIP
+
+
+def _hip_check(code: int, what: str):
+    if code != 0:
+        raise RuntimeError(f"{what} failed with HIP error {code}")
+
+
+def set_device(index: int = 0):
+    _hip_check(hip().hipSetDevice(int(index)), "hipSetDevice")
+
+
+def device_synchronize():
+    """Wait for all work of the library's HIP runtime on the current device."""
+    _hip_check(hip().hipDeviceSynchronize(), "hipDeviceSynchronize")
+
+
+class Stream:
+    """A HIP stream of the library's runtime (default priority; non-blocking with respect to
+    the null stream).  ``handle`` is what ``MPS(stream=...)`` takes."""
+
+    def __init__(self):
+        self.handle = ctypes.c_void_p()
+        _hip_check(hip().hipStreamCreateWithFlags(ctypes.byref(self.handle), 1),
+                   "hipStreamCreateWithFlags")
+
+    def synchronize(self):
+        _hip_check(hip().hipStreamSynchronize(self.handle), "hipStreamSynchronize")
+
+    def close(self):
+        if self.handle:
+            hip().hipStreamSynchronize(self.handle)
+            hip().hipStreamDestroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+
 def default_stream():
-    """HIP stream of torch's current device when the caller has imported torch and a GPU
-    is visible; otherwise None (the null stream).  torch is never imported here."""
-    torch = sys.modules.get("torch")
-    if torch is not None:
-        try:
-            if torch.cuda.is_available():
-                return torch.cuda.current_stream().cuda_stream
-        except Exception:  # noqa: BLE001 - torch is optional plumbing
-            pass
+    """The null stream of the library's runtime (None)."""
     return None
 
 
@@ -166,6 +219,8 @@ class MPS:
         self.n_sites = [int(x) for x in n_sites]
         self.chi_cap = [int(x) for x in chi_cap]
         self.precision = precision
+        if isinstance(stream, Stream):
+            stream = stream.handle.value
         self.stream = default_stream() if stream is None else stream
         self._h = ctypes.c_void_p()
         _check(lib().ptebd_mps_create(len(n_sites), _ptr(n_sites, ctypes.c_int32),

@@ -260,14 +260,12 @@ def test_overlap_of_handles_on_different_streams():
     """Two handles on two different HIP streams: the overlap query runs every kernel on the
     first handle's stream (the second's site tensors are staged in the first's scratch), so
     the result matches the oracle."""
-    import torch
-
     n = 12
     ga, la = inputs.random_vidal_state(n, 16, seed=31)
     gb, lb = inputs.random_vidal_state(n, 16, seed=32)
-    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
-    ma = ptebd.MPS(n, 16, "fp64", stream=sa.cuda_stream)
-    mb = ptebd.MPS(n, 16, "fp32", stream=sb.cuda_stream)
+    sa, sb = ptebd.Stream(), ptebd.Stream()
+    ma = ptebd.MPS(n, 16, "fp64", stream=sa)
+    mb = ptebd.MPS(n, 16, "fp32", stream=sb)
     ma.import_state(ga, la)
     mb.import_state(gb, lb)
     a, b = po.VidalMPS(ga, la), to_oracle(mb)
@@ -279,3 +277,5 @@ def test_overlap_of_handles_on_different_streams():
         assert abs(ov2 - np.conj(ref)) <= 1e-12 * po.norm(a) * po.norm(b)
     ma.close()
     mb.close()
+    sa.close()
+    sb.close()
