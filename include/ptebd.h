@@ -312,6 +312,25 @@ int ptebd_svd_batched(int precision, int batch, int m, int n, const double* a, d
                       double* u, double* vh, int32_t* sweeps, int max_sweeps,
                       double tol_factor, void* hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the batched SVD of ptebd_svd_batched, with the same
+ * arguments, results and errors, that allocates nothing.  Every device buffer it needs (work
+ * and rotation matrices, descriptors, per-matrix outputs, input and output staging) lies in
+ * one fixed array of PTEBD_NOALLOC_SCRATCH_BYTES per device, which the library holds until the
+ * process ends; the host arrays are the caller's and are copied directly.  The need grows
+ * with batch * (16 m n + 16 min(m,n) (m + n) + e min(m,n) max(m,n) + e min(m,n)^2) bytes
+ * (e = 16 for FP64, 8 for FP32) plus small per-matrix outputs; a batch that does not fit is
+ * rejected with EINVAL (the message gives the bytes it would need) before any device work.
+ * Example: one 512 x 512 matrix needs about 20 MiB in FP64 and 16 MiB in FP32.  All calls on
+ * one device share its array: calls that overlap in time on one device race (serialize them).
+ * Each call writes everything it reads first, so no state carries over between calls.
+ */
+#define PTEBD_NOALLOC_SCRATCH_BYTES (32u << 20)
+int ptebd_svd_batched_noalloc(int precision, int batch, int m, int n, const double* a,
+                              double* s, double* u, double* vh, int32_t* sweeps, int max_sweeps,
+                              double tol_factor, void* hip_stream);
+
 /* ------------------------------------------------------------------ kernel timing
  * When profiling is on, every hot-path kernel launch of the handle is bracketed by HIP
  * events on the handle's stream, and per kernel class the library accumulates the device

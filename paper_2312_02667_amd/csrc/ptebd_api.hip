@@ -823,6 +823,32 @@ void site_a(const ptebd_mps* h, int s, int q, const double* lam_left, const doub
 
 }  // namespace
 
+namespace ptebd {
+
+int report_error(int code, const char* msg) { return fail(code, msg); }
+
+size_t layer_out_bytes(int n, int cmax) { return out_layout(n, cmax).total; }
+
+LayerOut layer_out_at(void* base, int n, int cmax) {
+  return make_layer_out(base, out_layout(n, cmax), cmax);
+}
+
+template <class T>
+int jacobi_sweeps(hipStream_t stream, const GateDesc* d_desc, int n, int max_c,
+                  const LayerOut& lo, int precision, int max_sweeps, double tol_factor,
+                  int inner_sweeps, double inner_repeat, int sort_pairs, int32_t* h_counter,
+                  int* n_unconverged) {
+  return run_jacobi<T>(stream, d_desc, n, max_c, lo, precision, max_sweeps, tol_factor,
+                       inner_sweeps, inner_repeat, sort_pairs, h_counter, n_unconverged, nullptr);
+}
+
+template int jacobi_sweeps<float>(hipStream_t, const GateDesc*, int, int, const LayerOut&, int,
+                                  int, double, int, double, int, int32_t*, int*);
+template int jacobi_sweeps<double>(hipStream_t, const GateDesc*, int, int, const LayerOut&, int,
+                                   int, double, int, double, int, int32_t*, int*);
+
+}  // namespace ptebd
+
 // ============================================================================ C ABI
 extern "C" {
 

@@ -174,4 +174,19 @@ void launch_init_product(void* gamma_base, const size_t* d_gamma_offsets, int n_
                          double* lam_base, const size_t* d_lam_offsets, int n_bonds,
                          hipStream_t stream);
 
+// Host helpers of the runtime (ptebd_api.hip), shared with the allocation-free entry point.
+// Sets the thread-local last error and returns code.
+int report_error(int code, const char* msg);
+// Bytes of the per-gate output block of a batch of n gates of at most cmax columns, and the
+// block laid out at base (256-byte aligned pieces).
+size_t layer_out_bytes(int n, int cmax);
+LayerOut layer_out_at(void* base, int n, int cmax);
+// The Jacobi sweeps of the batched SVD on descriptors already on the device (init kernel,
+// rounds, a convergence check and one 4-byte read-back into h_counter per sweep).
+template <class T>
+int jacobi_sweeps(hipStream_t stream, const GateDesc* d_desc, int n, int max_c,
+                  const LayerOut& lo, int precision, int max_sweeps, double tol_factor,
+                  int inner_sweeps, double inner_repeat, int sort_pairs, int32_t* h_counter,
+                  int* n_unconverged);
+
 }  // namespace ptebd

@@ -115,6 +115,10 @@ _SIGS = {
     "ptebd_svd_batched": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           _dp, _dp, _dp, _dp, _i32p, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_void_p]),
+    "ptebd_svd_batched_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, _dp, _dp, _dp, _dp, _i32p,
+                                                  ctypes.c_int, ctypes.c_double,
+                                                  ctypes.c_void_p]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -413,9 +417,13 @@ class MPS:
         return out.view(np.complex128).reshape(m, n)
 
 
+NOALLOC_SCRATCH_BYTES = 32 << 20  # PTEBD_NOALLOC_SCRATCH_BYTES
+
+
 def svd_batched(a, precision: str = "fp64", max_sweeps: int = 30, tol_factor: float = 4.0,
-                stream=None):
-    """Batched SVD of complex matrices a[b] (m x n) on the device: (s, u, vh, sweeps)."""
+                stream=None, noalloc: bool = False):
+    """Batched SVD of complex matrices a[b] (m x n) on the device: (s, u, vh, sweeps, status).
+    ``noalloc`` calls the entry point that allocates no device memory (fixed scratch array)."""
     a = np.ascontiguousarray(np.asarray(a, np.complex128))
     if a.ndim == 2:
         a = a[None]
@@ -426,7 +434,8 @@ def svd_batched(a, precision: str = "fp64", max_sweeps: int = 30, tol_factor: fl
     vh = np.zeros((batch, k, n), np.complex128)
     sw = np.zeros(batch, np.int32)
     stream = default_stream() if stream is None else stream
-    code = _check(lib().ptebd_svd_batched(
+    fn = lib().ptebd_svd_batched_noalloc if noalloc else lib().ptebd_svd_batched
+    code = _check(fn(
         PRECISIONS[precision], batch, m, n, _ptr(a.view(np.float64), ctypes.c_double),
         _ptr(s, ctypes.c_double), _ptr(u.view(np.float64), ctypes.c_double),
         _ptr(vh.view(np.float64), ctypes.c_double), _ptr(sw, ctypes.c_int32), int(max_sweeps),

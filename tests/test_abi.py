@@ -104,3 +104,21 @@ def test_every_declaration_cites_or_documents():
         # the text between the previous declaration's end and this one holds a comment
         prev = max(head.rfind(";"), head.rfind("{"))
         assert "*/" in head[prev:], name
+
+
+def test_svd_noalloc_rejects_oversized_batches_before_device_work():
+    """The allocation-free SVD refuses a batch that does not fit its fixed scratch array
+    (one 1024 x 1024 FP64 matrix needs well over 32 MiB) with EINVAL and a message, before it
+    touches the device, so this runs without a GPU."""
+    lib = ptebd.lib()
+    a = np.zeros(8)
+    s = np.zeros(2)
+    p = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ps = s.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.ptebd_svd_batched_noalloc(0, 1, 1024, 1024, p, ps, None, None, None, 30, 4.0,
+                                         None) == ptebd.EINVAL
+    assert "scratch" in lib.ptebd_last_error().decode()
+    assert lib.ptebd_svd_batched_noalloc(0, 0, 2, 2, p, ps, None, None, None, 30, 4.0,
+                                         None) == ptebd.EINVAL
+    assert lib.ptebd_svd_batched_noalloc(ptebd.BF16X3, 1, 2, 2, p, ps, None, None, None, 30, 4.0,
+                                         None) == ptebd.EINVAL
