@@ -133,9 +133,10 @@ int ptebd_mps_destroy(ptebd_mps_t h);
 /* Controls of the batched one-sided block Jacobi SVD of a handle. */
 typedef struct {
   int max_sweeps;       /* >= 1, default 30 */
-  double tol_factor;    /* > 0, default 4: a pair of columns counts as orthogonal when
-                           |x^H y| <= tol_factor * eps * sqrt(rows) * |x| |y|, eps the unit
-                           roundoff of the precision */
+  double tol_factor;    /* > 0, default 1 for FP32 and 4 for FP64: a pair of columns counts
+                           as orthogonal when |x^H y| <= max(tol_factor sqrt(rows), 8) eps
+                           |x| |y|, eps the unit roundoff of the precision (the floor: a short
+                           pair's cosine is not computed more accurately than that) */
   int inner_sweeps;     /* in [1, 64]: at most this many cyclic sweeps over each 32x32 block
                            pair's Gram matrix (default 2 for FP32, 1 for FP64) */
   double inner_repeat;  /* >= 0: a further inner sweep runs only while the previous one rotated
@@ -344,6 +345,9 @@ int ptebd_svd_batched_noalloc(int precision, int batch, int m, int n, const doub
  *   FINALIZE   column norms: reads W (R C complex elements); no MFMA flops counted.
  *   WRITEBACK  reads the k kept columns, writes both Gammas (2 k (chi_q + chi_{q+2})
  *              complex elements each way).
+ * When a batch runs as two halves on two streams (ptebd_svd_params.streams), a class's time
+ * is the union of its intervals on both streams, each half's launch counting as half a
+ * launch, so that time and launches stand for the work over all gates.
  * ptebd_set_profiling(h, 1) enables and resets; ptebd_get_kernel_stats reads a class. */
 #define PTEBD_KERNEL_THETA 0
 #define PTEBD_KERNEL_JACOBI 1

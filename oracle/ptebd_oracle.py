@@ -174,8 +174,20 @@ def ptsu_step(mps: VidalMPS, cutoff: float) -> None:
         tsu(mps, q, cutoff)
 
 
+def _gate_on_its_bond(task):
+    """One gate of a layer applied to its own two sites: (Gamma[q], Gamma[q+1], Lambda[q],
+    Lambda[q+1], Lambda[q+2], gate, chi_max, cutoff, stabilize, eps_reading) -> (the two new
+    Gammas, the new Lambda[q+1] without nu, stats).  A gate reads and writes nothing else
+    (Sec. II.C), which is what lets the gates of a layer run in any order or at once."""
+    gq, gq1, ll, lm, lr, gate, chi_max, cutoff, stabilize, eps_reading = task
+    local = VidalMPS([gq, gq1], [ll, lm, lr])
+    st = bond_update(local, 0, gate, chi_max, cutoff, stabilize, eps_reading, apply_nu=False)
+    return local.gam[0], local.gam[1], local.lam[1], st
+
+
 def apply_layer(mps: VidalMPS, bonds, gates, chi_max: int, cutoff: float = 1e-12,
-                ptsu_steps: int = 0, stabilize: bool = True, eps_reading: str = "literal"):
+                ptsu_steps: int = 0, stabilize: bool = True, eps_reading: str = "literal",
+                map_fn=None):
     """One pTEBD step (Algorithm 1): the TEBD procedure on every gate of the layer, each bond
     cut to chi_max.  If some gate's rank exceeded chi_max ("if chi~ > chi") the layer is
     compressed by IPMC (Sec. III.E): the truncated bonds' Schmidt values are multiplied by
@@ -184,7 +196,8 @@ def apply_layer(mps: VidalMPS, bonds, gates, chi_max: int, cutoff: float = 1e-12
     branch of Algorithm 1; the cutoff still drops values below cutoff * sigma_1).
 
     Gates touch disjoint sites and read only Lambda[q], Lambda[q+2], which no gate of the same
-    layer writes, so the order of the gates does not matter; they are processed in ascending q.
+    layer writes, so the order of the gates does not matter; they are processed in ascending q,
+    or, with ``map_fn`` (a map over the per-gate tasks, e.g. a thread pool's), all at once.
     Returns (list of per-gate stats in ascending-q order, triggered flag); each gate's "nu"
     is the factor actually applied.
     """
@@ -192,9 +205,18 @@ def apply_layer(mps: VidalMPS, bonds, gates, chi_max: int, cutoff: float = 1e-12
     _check_disjoint(mps.n_sites, bonds)
     order = np.argsort(bonds, kind="stable")
     stats = [None] * len(bonds)
-    for idx in order:
-        stats[idx] = bond_update(mps, bonds[idx], gates[idx], chi_max, cutoff, stabilize,
-                                 eps_reading, apply_nu=False)
+    if map_fn is None:
+        for idx in order:
+            stats[idx] = bond_update(mps, bonds[idx], gates[idx], chi_max, cutoff, stabilize,
+                                     eps_reading, apply_nu=False)
+    else:
+        tasks = [(mps.gam[q], mps.gam[q + 1], mps.lam[q], mps.lam[q + 1], mps.lam[q + 2],
+                  gates[idx], chi_max, cutoff, stabilize, eps_reading)
+                 for idx, q in ((i, bonds[i]) for i in order)]
+        for idx, (g0, g1, lm, st) in zip(order, map_fn(_gate_on_its_bond, tasks)):
+            q = bonds[idx]
+            mps.gam[q], mps.gam[q + 1], mps.lam[q + 1] = g0, g1, lm
+            stats[idx] = st
     triggered = any(st["r"] > chi_max for st in stats)
     for idx, st in enumerate(stats):
         if triggered:

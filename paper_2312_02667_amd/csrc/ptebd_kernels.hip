@@ -494,7 +494,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   __syncthreads();
   mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   if constexpr (kSq) mx = sqrt(mx);
-  const bool rotate = mx > tol_scale * sqrt((double)R);
+  // Orthogonality threshold tol_factor u sqrt(R), but never below 8 u: the cosine of a
+  // short column pair cannot be computed more accurately than a few units of u.
+  constexpr double kUnit = sizeof(T) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+  const double thr = fmax(tol_scale * sqrt((double)R), 8.0 * kUnit);
+  const bool rotate = mx > thr;
   if (tid == 0) {
     atomicMax(&out.offbits[g], __float_as_uint((float)mx));
     uint32_t* wk = out.work + ((size_t)g * out.nslot + blockIdx.x) * 2;  // this pair's slot
@@ -512,7 +516,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   // ---- cyclic Jacobi on the 32x32 Hermitian G; Q accumulates the rotations.  The
   // threshold sits well below the outer tolerance so that a pair the outer test calls
   // unconverged is always rotated.
-  const double inner_tol = 0.125 * tol_scale * sqrt((double)R);
+  const double inner_tol = 0.125 * thr;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
     cplx<T> z;
@@ -760,7 +764,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
 }
 
 // After a sweep: a gate whose largest relative off-diagonal stayed at or below
-// tol_factor * u * sqrt(R) is converged.  counters[sweep & 1] counts the others.
+// max(tol_factor sqrt(R), 8) u is converged.  counters[sweep & 1] counts the others.
 __global__ void sweep_check_kernel(const GateDesc* __restrict__ descs, int n_gates, int sweep,
                                    double tol_factor, double unit_roundoff, LayerOut out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -770,7 +774,7 @@ __global__ void sweep_check_kernel(const GateDesc* __restrict__ descs, int n_gat
   out.sweeps[g] += 1;
   const float off = __uint_as_float(out.offbits[g]);
   out.offbits[g] = 0u;
-  const double tol = tol_factor * unit_roundoff * sqrt((double)descs[g].R);
+  const double tol = fmax(tol_factor * sqrt((double)descs[g].R), 8.0) * unit_roundoff;
   if ((double)off <= tol)
     out.conv[g] = 1;
   else

@@ -201,7 +201,7 @@ def test_kernel_profiling_counts_launches():
 def test_svd_params_round_trip_and_validation():
     m = ptebd.MPS(6, 8, "fp32")
     p = m.svd_params()
-    assert p == {"max_sweeps": 30, "tol_factor": 4.0, "inner_sweeps": 2, "inner_repeat": 1e-2,
+    assert p == {"max_sweeps": 30, "tol_factor": 1.0, "inner_sweeps": 2, "inner_repeat": 1e-2,
                  "sort_pairs": 1, "precondition": 1, "streams": 2}
     m.set_svd_params(inner_sweeps=3, inner_repeat=0.0, precondition=False)
     q = m.svd_params()
@@ -217,6 +217,7 @@ def test_svd_params_round_trip_and_validation():
     m.close()
     d = ptebd.MPS(6, 8, "fp64")
     assert d.svd_params()["inner_sweeps"] == 1 and d.svd_params()["inner_repeat"] == 0.0
+    assert d.svd_params()["tol_factor"] == 4.0
     d.close()
 
 

@@ -519,3 +519,23 @@ def test_sampling_special_cases_and_frequencies():
     idx = bits.astype(np.int64) @ (1 << np.arange(n - 1, -1, -1))
     freq = np.bincount(idx, minlength=2 ** n) / s
     assert np.all(np.abs(freq - prob) <= 5 * np.sqrt(prob * (1 - prob) / s) + 1e-12)
+
+
+def test_layer_with_a_parallel_map_equals_the_ordered_layer():
+    """The gates of a layer act on disjoint sites (Sec. II.C): applying them all at once
+    through a thread pool gives the ordered result (Lambda, Gamma and stats)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    n = 12
+    layers = inputs.brickwork_circuit(n, 8, seed=6)
+    a, b = po.product_state(n), po.product_state(n)
+    with ThreadPoolExecutor(4) as ex:
+        for bonds, gates in layers:
+            sa, ta = po.apply_layer(a, bonds, gates, chi_max=6, eps_reading="complement")
+            sb, tb = po.apply_layer(b, bonds, gates, chi_max=6, eps_reading="complement",
+                                    map_fn=ex.map)
+            assert ta == tb
+            assert [x["k"] for x in sa] == [x["k"] for x in sb]
+            assert np.allclose([x["nu"] for x in sa], [x["nu"] for x in sb], rtol=0, atol=1e-14)
+    assert max(float(np.max(np.abs(x - y))) for x, y in zip(a.lam, b.lam)) < 1e-13
+    assert abs(po.overlap(a, b) - po.norm(a) ** 2) < 1e-12 * po.norm(a) ** 2
