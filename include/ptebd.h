@@ -158,6 +158,17 @@ typedef struct {
                            fills the GPU while the other's launches drain.  The call returns
                            once both streams have drained.  Results are the same bit for
                            bit as with 1. */
+  int block_cols;       /* 16 (default) or 32, FP32 handles only: columns per Jacobi block.
+                           A round pairs blocks of this width; 32-column blocks take fewer
+                           sweeps and move half the bytes per sweep, with a 64 x 64 inner
+                           problem per pair.  Results differ from 16 in the rounding only. */
+  int graphs;           /* 0/1, default 1: each Jacobi sweep (its rounds and convergence check)
+                           runs as one launch of a captured HIP graph, instantiated once per
+                           batch shape and cached in the handle.  Either way the sweeps are
+                           device-driven: the next sweep is queued before the host reads the
+                           previous sweep's count of unconverged SVDs, and its launches return
+                           at once when that count was zero.  Results are the same bit for bit
+                           with 0. */
 } ptebd_svd_params;
 
 /* Read (get) or replace (set) the SVD controls of a handle.  set validates every field

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libptebd.so")
 SOURCES = ["ptebd_api.hip", "ptebd_kernels.hip", "ptebd_queries.hip", "ptebd_sample.hip",
-           "ptebd_precond.hip", "ptebd_noalloc.hip"]
+           "ptebd_precond.hip", "ptebd_noalloc.hip", "ptebd_jacobi64.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -119,7 +119,8 @@ struct Prof {
   struct Pend {
     int kind;
     hipEvent_t a, b;
-    int count;  // launches the interval stands for
+    int count;  // launches the interval stands for (-1: a sweep queued past convergence,
+                // whose early-exit launches are not counted)
   };
   std::vector<hipEvent_t> pool;
   std::vector<Pend> pending;
@@ -154,7 +155,7 @@ struct Prof {
       std::vector<std::pair<float, float>> iv;
       double count = 0.0;
       for (const Span& sp : spans) {
-        if (sp.kind != kind) continue;
+        if (sp.kind != kind || sp.count < 0) continue;
         float a = 0.f, b = 0.f;
         if (ref && hipEventElapsedTime(&a, ref, sp.a) == hipSuccess &&
             hipEventElapsedTime(&b, ref, sp.b) == hipSuccess)
@@ -189,7 +190,7 @@ struct Prof {
   void harvest() {
     for (const Pend& p : pending) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      if (p.count >= 0 && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         st[p.kind].total_ms += ms;
         st[p.kind].launches += p.count;
       }
@@ -241,6 +242,28 @@ int timed_span(Prof* pf, int kind, hipStream_t stream, double count, F fn) {
   return PTEBD_OK;
 }
 
+// Instantiated graphs of one Jacobi sweep (its rounds and the convergence check), keyed by
+// every argument the captured launches carry; captured on a private stream and launched on
+// the pipeline's stream.  A few entries suffice (a layer's shapes repeat); the least recently
+// used one is replaced.
+struct SweepGraphs {
+  struct Entry {
+    std::string key;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  std::vector<Entry> entries;
+  hipStream_t capture = nullptr;
+  uint64_t tick = 0;
+  static constexpr size_t kMax = 12;
+  void release() {
+    for (Entry& e : entries) (void)hipGraphExecDestroy(e.exec);
+    entries.clear();
+    if (capture) (void)hipStreamDestroy(capture);
+    capture = nullptr;
+  }
+};
+
 double unit_roundoff(int precision) {
   return precision == PTEBD_FP64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
 }
@@ -264,6 +287,10 @@ struct ptebd_mps {
   int sort_pairs = 1;
   int precondition = 1;  // FP32 handles only
   int streams = 2;       // Jacobi sweeps of a large batch on two streams
+  int block_cols = 16;   // Jacobi block width (32: FP32 handles only)
+  int graphs = 1;        // each Jacobi sweep as one captured HIP graph
+  SweepGraphs sweep_graphs;
+  hipEvent_t ev_sweep[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [pipeline][parity]
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // second stream of the Jacobi sweeps and its fork / join events, created on first use
   hipStream_t stream2 = nullptr;
@@ -341,6 +368,7 @@ LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
   o.rstart = (int32_t*)(b + L.rstart);
   o.nbmax = L.nbmax;
   o.triangular = 0;
+  o.block_cols = 16;
   o.cmax = cmax;
   return o;
 }
@@ -370,34 +398,232 @@ struct SplitStreams {
   int32_t* counters2;  // device, 4 ints
 };
 
-// Sweeps of the block Jacobi SVD on descriptors already on the device, on one stream.
+// One round of the block Jacobi with the block width of lo (32-column blocks: FP32 only).
 template <class T>
-int run_jacobi(hipStream_t stream, const GateDesc* d_desc, int n, int max_c, const LayerOut& lo,
-               int precision, int max_sweeps, double tol_factor, int inner_sweeps,
-               double inner_repeat, int sort_pairs, int32_t* h_counter, int* n_unconverged,
-               Prof* pf) {
-  ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
-  int nb = (max_c + 15) / 16;
-  int nbp = nb + (nb & 1);
-  if (nbp < 2) nbp = 2;
-  const double u = unit_roundoff(precision);
-  int remaining = n;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int round = 0; round < nbp - 1; ++round)
-      timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] {
-        ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_factor * u, inner_sweeps,
-                                      inner_repeat, sort_pairs, stream);
-      });
-    ptebd::launch_sweep_check(d_desc, n, sweep, tol_factor, u, lo, stream);
+void launch_round(const GateDesc* d_desc, int n, int round, int nbp, const LayerOut& lo,
+                  double tol_scale, int inner_sweeps, double inner_repeat, int sort_pairs,
+                  int prev_slot, hipStream_t stream) {
+  if (sizeof(T) == 4 && lo.block_cols == 32)
+    ptebd::launch_jacobi_round64(d_desc, n, round, nbp, lo, tol_scale, inner_sweeps,
+                                 inner_repeat, sort_pairs, prev_slot, stream);
+  else
+    ptebd::launch_jacobi_round<T>(d_desc, n, round, nbp, lo, tol_scale, inner_sweeps,
+                                  inner_repeat, sort_pairs, prev_slot, stream);
+}
+
+// Players of one sweep's tournament: the block count of max_c columns, made even.
+int tournament_players(int max_c, int block_cols) {
+  const int nb = (max_c + block_cols - 1) / block_cols;
+  return std::max(2, nb + (nb & 1));
+}
+
+// What one pipeline's sweeps need: its gates, their outputs and the SVD controls.
+struct SweepArgs {
+  const GateDesc* d;
+  int n, nbp;
+  LayerOut lo;
+  double tol_factor, u;
+  int inner_sweeps;
+  double inner_repeat;
+  int sort_pairs;
+};
+
+template <class X>
+void append_key(std::string& k, const X& x) {
+  k.append(reinterpret_cast<const char*>(&x), sizeof(X));
+}
+
+// Sweep s of a pipeline on `stream`: its nbp - 1 rounds and the convergence check that counts
+// the unconverged gates into lo.counters[s & 1].  Every round of a sweep s > 0 returns at once
+// when the previous sweep's count is zero, so a sweep queued before the host has read that
+// count costs only its empty launches.  With a graph cache (sg), the sweep is one launch of a
+// captured graph; the sweeps s > 0 of one parity share a graph.
+template <class T>
+int launch_sweep(SweepGraphs* sg, hipStream_t stream, const SweepArgs& a, int s) {
+  const int prev_slot = s == 0 ? -1 : ((s - 1) & 1);
+  auto body = [&](hipStream_t st) {
+    for (int r = 0; r < a.nbp - 1; ++r)
+      launch_round<T>(a.d, a.n, r, a.nbp, a.lo, a.tol_factor * a.u, a.inner_sweeps,
+                      a.inner_repeat, a.sort_pairs, prev_slot, st);
+    ptebd::launch_sweep_check(a.d, a.n, s & 1, a.tol_factor, a.u, a.lo, st);
+  };
+  if (!sg) {
+    body(stream);
     PT_HIP(hipGetLastError());
-    PT_HIP(hipMemcpyAsync(h_counter, lo.counters + (sweep & 1), sizeof(int32_t),
-                          hipMemcpyDeviceToHost, stream));
-    PT_HIP(hipStreamSynchronize(stream));
-    if (pf) pf->harvest();
-    remaining = *h_counter;
-    if (remaining == 0) break;
+    return PTEBD_OK;
   }
-  *n_unconverged = remaining;
+  std::string key;
+  const int variant = s == 0 ? 0 : 1 + (s & 1);
+  append_key(key, (int)sizeof(T));
+  append_key(key, a.d);
+  append_key(key, a.n);
+  append_key(key, a.nbp);
+  append_key(key, a.lo);
+  append_key(key, a.tol_factor);
+  append_key(key, a.u);
+  append_key(key, a.inner_sweeps);
+  append_key(key, a.inner_repeat);
+  append_key(key, a.sort_pairs);
+  append_key(key, variant);
+  SweepGraphs::Entry* hit = nullptr;
+  for (auto& e : sg->entries)
+    if (e.key == key) hit = &e;
+  if (!hit) {
+    if (!sg->capture)
+      PT_HIP(hipStreamCreateWithFlags(&sg->capture, hipStreamNonBlocking));
+    PT_HIP(hipStreamBeginCapture(sg->capture, hipStreamCaptureModeThreadLocal));
+    body(sg->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t launched = hipGetLastError();
+    const hipError_t ended = hipStreamEndCapture(sg->capture, &graph);
+    if (launched != hipSuccess || ended != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(PTEBD_EDEVICE, "capture of a Jacobi sweep graph failed");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t inst = hipGraphInstantiateWithFlags(&exec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (inst != hipSuccess || !exec)
+      return fail(PTEBD_EDEVICE, "instantiation of a Jacobi sweep graph failed");
+    if (sg->entries.size() >= SweepGraphs::kMax) {
+      auto lru = std::min_element(sg->entries.begin(), sg->entries.end(),
+                                  [](const SweepGraphs::Entry& x, const SweepGraphs::Entry& y) {
+                                    return x.used < y.used;
+                                  });
+      (void)hipGraphExecDestroy(lru->exec);
+      sg->entries.erase(lru);
+    }
+    sg->entries.push_back({key, exec, 0});
+    hit = &sg->entries.back();
+  }
+  hit->used = ++sg->tick;
+  PT_HIP(hipGraphLaunch(hit->exec, stream));
+  return PTEBD_OK;
+}
+
+// A pipeline's sweeps driven from the device side: sweep s + 1 is queued before the host
+// reads sweep s's count of unconverged gates (one 4-byte copy and an event per sweep), so
+// the device never waits for the host between sweeps; a sweep queued past convergence
+// returns at once and is not counted in the profile.
+template <class T>
+struct SweepDriver {
+  SweepGraphs* sg;
+  hipStream_t stream;
+  SweepArgs a;
+  int max_sweeps;
+  int32_t* h_cnt;      // two pinned host ints (sweep parity)
+  hipEvent_t ev[2];    // recorded after each sweep's count copy
+  Prof* pf;
+  double span_count;   // > 0: profile as a span (two concurrent pipelines), else per sweep
+  int issued = 0;      // sweeps queued
+  int checked = -1;    // last sweep whose count was read
+  long prof_idx[64];   // profile entry of each queued sweep (by sweep index mod 64)
+
+  int issue(int s) {
+    prof_idx[s & 63] = -1;
+    const bool prof = pf && pf->on;
+    if (prof && span_count > 0.0) {
+      prof_idx[s & 63] = pf->ref ? (long)pf->spans.size() : -1;
+      int st_ = PTEBD_OK;
+      PT_CHECK(timed_span(pf, PTEBD_KERNEL_JACOBI, stream, span_count,
+                          [&] { st_ = launch_sweep<T>(sg, stream, a, s); }));
+      PT_CHECK(st_);
+    } else if (prof) {
+      prof_idx[s & 63] = (long)pf->pending.size();
+      int st_ = PTEBD_OK;
+      timed(pf, PTEBD_KERNEL_JACOBI, stream, [&] { st_ = launch_sweep<T>(sg, stream, a, s); });
+      PT_CHECK(st_);
+      if ((size_t)prof_idx[s & 63] < pf->pending.size())
+        pf->pending[prof_idx[s & 63]].count = a.nbp - 1;
+      else
+        prof_idx[s & 63] = -1;
+    } else {
+      PT_CHECK(launch_sweep<T>(sg, stream, a, s));
+    }
+    PT_HIP(hipMemcpyAsync(h_cnt + (s & 1), a.lo.counters + (s & 1), sizeof(int32_t),
+                          hipMemcpyDeviceToHost, stream));
+    PT_HIP(hipEventRecord(ev[s & 1], stream));
+    issued = s + 1;
+    return PTEBD_OK;
+  }
+  // queue the first sweeps
+  int start() {
+    PT_CHECK(issue(0));
+    if (max_sweeps > 1) PT_CHECK(issue(1));
+    return PTEBD_OK;
+  }
+  // wait for the next unread sweep; *done = 1 with *rem the final count when the pipeline
+  // has converged or used its sweeps, else the following sweep is queued
+  int step(int* done, int* rem) {
+    const int s = checked + 1;
+    PT_HIP(hipEventSynchronize(ev[s & 1]));
+    checked = s;
+    *rem = h_cnt[s & 1];
+    if (*rem == 0 || s + 1 >= max_sweeps) {
+      *done = 1;
+      // a sweep queued after this one found the batch converged and did nothing
+      for (int t = s + 1; t < issued; ++t) {
+        const long idx = prof_idx[t & 63];
+        if (idx < 0 || !pf) continue;
+        if (span_count > 0.0) {
+          if ((size_t)idx < pf->spans.size()) pf->spans[idx].count = -1.0;
+        } else if ((size_t)idx < pf->pending.size()) {
+          pf->pending[idx].count = -1;
+        }
+      }
+      return PTEBD_OK;
+    }
+    *done = 0;
+    if (s + 2 < max_sweeps && issued <= s + 2) PT_CHECK(issue(s + 2));
+    return PTEBD_OK;
+  }
+};
+
+int sweep_events(ptebd_mps* h, int k, hipEvent_t ev[2]) {
+  for (int j = 0; j < 2; ++j) {
+    if (!h->ev_sweep[k][j])
+      PT_HIP(hipEventCreateWithFlags(&h->ev_sweep[k][j], hipEventDisableTiming));
+    ev[j] = h->ev_sweep[k][j];
+  }
+  return PTEBD_OK;
+}
+
+// Sweeps of the block Jacobi SVD on descriptors already on the device, on one stream.  With
+// a handle: the device-driven sweeps of SweepDriver (graphs when the handle enables them);
+// without one (the stand-alone batched SVD entry points): one sweep at a time, each followed
+// by a read of its count.
+template <class T>
+int run_jacobi(ptebd_mps* h, hipStream_t stream, const GateDesc* d_desc, int n, int max_c,
+               const LayerOut& lo, int precision, int max_sweeps, double tol_factor,
+               int inner_sweeps, double inner_repeat, int sort_pairs, int32_t* h_counter,
+               int* n_unconverged, Prof* pf) {
+  ptebd::launch_jacobi_init<T>(d_desc, n, max_c, lo, stream);
+  const SweepArgs a{d_desc, n, tournament_players(max_c, lo.block_cols), lo, tol_factor,
+                    unit_roundoff(precision), inner_sweeps, inner_repeat, sort_pairs};
+  if (!h) {
+    int remaining = n;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      PT_CHECK(launch_sweep<T>(nullptr, stream, a, sweep));
+      PT_HIP(hipMemcpyAsync(h_counter, lo.counters + (sweep & 1), sizeof(int32_t),
+                            hipMemcpyDeviceToHost, stream));
+      PT_HIP(hipStreamSynchronize(stream));
+      remaining = *h_counter;
+      if (remaining == 0) break;
+    }
+    *n_unconverged = remaining;
+    return PTEBD_OK;
+  }
+  SweepDriver<T> drv{h->graphs ? &h->sweep_graphs : nullptr, stream, a, max_sweeps, h_counter,
+                     {nullptr, nullptr}, pf, 0.0};
+  PT_CHECK(sweep_events(h, 0, drv.ev));
+  PT_CHECK(drv.start());
+  int done = 0, rem = n;
+  while (!done) PT_CHECK(drv.step(&done, &rem));
+  if (pf) {
+    PT_HIP(hipStreamSynchronize(stream));
+    pf->harvest();
+  }
+  *n_unconverged = rem;
   return PTEBD_OK;
 }
 
@@ -440,9 +666,7 @@ int run_split(ptebd_mps* h, const SplitStreams& sp, const GateDesc* d_desc,
   ptebd::PrecondOut pp[2] = {po, po};
   pp[1].ps += (size_t)n1 * po.cmax;
   pp[1].gmax += n1;
-  int nb = (max_c + 15) / 16;
-  int nbp = nb + (nb & 1);
-  if (nbp < 2) nbp = 2;
+  const int nbp = tournament_players(max_c, lo.block_cols);
   const double u = unit_roundoff(h->precision);
   if (prof) {
     pf->ref = pf->get();
@@ -473,18 +697,6 @@ int run_split(ptebd_mps* h, const SplitStreams& sp, const GateDesc* d_desc,
     ptebd::launch_jacobi_init<T>(d_jdesc + off[k], nn[k], max_c, oo[k], st[k]);
     return PTEBD_OK;
   };
-  auto sweep = [&](int k, int sw) {
-    const GateDesc* jd = d_jdesc + off[k];
-    PT_CHECK(timed_span(pf, PTEBD_KERNEL_JACOBI, st[k], 0.5 * (nbp - 1), [&] {
-      for (int round = 0; round < nbp - 1; ++round)
-        ptebd::launch_jacobi_round<T>(jd, nn[k], round, nbp, oo[k], h->tol_factor * u,
-                                      h->inner_sweeps, h->inner_repeat, h->sort_pairs, st[k]);
-    }));
-    ptebd::launch_sweep_check(jd, nn[k], sw, h->tol_factor, u, oo[k], st[k]);
-    PT_HIP(hipMemcpyAsync(h_counter + k, oo[k].counters + (sw & 1), sizeof(int32_t),
-                          hipMemcpyDeviceToHost, st[k]));
-    return PTEBD_OK;
-  };
   auto back = [&](int k) {
     const GateDesc* jd = d_jdesc + off[k];
     PT_CHECK(timed_span(pf, PTEBD_KERNEL_FINALIZE, st[k], 0.5,
@@ -498,26 +710,34 @@ int run_split(ptebd_mps* h, const SplitStreams& sp, const GateDesc* d_desc,
     }));
     return PTEBD_OK;
   };
-  int sw[2] = {0, 0};
+  // each half's sweeps run device-driven (SweepDriver); the host serves whichever half's
+  // next count is due, queueing that half's next sweep or its finalize and write-back
+  SweepDriver<T> drv[2] = {
+      {h->graphs ? &h->sweep_graphs : nullptr, st[0],
+       SweepArgs{d_jdesc, nn[0], nbp, oo[0], h->tol_factor, u, h->inner_sweeps,
+                 h->inner_repeat, h->sort_pairs},
+       h->max_sweeps, h_counter, {nullptr, nullptr}, pf, 0.5 * (nbp - 1)},
+      {h->graphs ? &h->sweep_graphs : nullptr, st[1],
+       SweepArgs{d_jdesc + off[1], nn[1], nbp, oo[1], h->tol_factor, u, h->inner_sweeps,
+                 h->inner_repeat, h->sort_pairs},
+       h->max_sweeps, h_counter + 2, {nullptr, nullptr}, pf, 0.5 * (nbp - 1)}};
   bool active[2] = {true, true};
   for (int k = 0; k < 2; ++k) {
+    PT_CHECK(sweep_events(h, k, drv[k].ev));
     PT_CHECK(front(k));
-    PT_CHECK(sweep(k, 0));
+    PT_CHECK(drv[k].start());
   }
   PT_HIP(hipGetLastError());
   int unconv = 0;
   while (active[0] || active[1]) {
     for (int k = 0; k < 2; ++k) {
       if (!active[k]) continue;
-      PT_HIP(hipStreamSynchronize(st[k]));
-      const int rem = h_counter[k];
-      ++sw[k];
-      if (rem == 0 || sw[k] >= h->max_sweeps) {
+      int done = 0, rem = 0;
+      PT_CHECK(drv[k].step(&done, &rem));
+      if (done) {
         active[k] = false;
         unconv += rem;
         PT_CHECK(back(k));
-      } else {
-        PT_CHECK(sweep(k, sw[k]));
       }
       PT_HIP(hipGetLastError());
     }
@@ -645,6 +865,7 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   const GateDesc* d_wdesc = pre ? d_desc + 2 * n : d_desc;
   LayerOut lo = make_layer_out(h->outbuf.p, L, cmax);
   lo.triangular = pre ? 1 : 0;  // the Jacobi then starts from X = R^H, lower triangular
+  lo.block_cols = sizeof(T) == 4 ? h->block_cols : 16;
   ptebd::PrecondOut po;
   po.ps = (int32_t*)((char*)h->outbuf.p + L.ps);
   po.gmax = (double*)((char*)h->outbuf.p + L.gmax);
@@ -668,7 +889,7 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
         ptebd::launch_xinit(d_jdesc, n, max_c, stream);
       });
     PT_HIP(hipGetLastError());
-    PT_CHECK(run_jacobi<T>(stream, d_jdesc, n, max_c, lo, h->precision, h->max_sweeps,
+    PT_CHECK(run_jacobi<T>(h, stream, d_jdesc, n, max_c, lo, h->precision, h->max_sweeps,
                            h->tol_factor, h->inner_sweeps, h->inner_repeat, h->sort_pairs,
                            (int32_t*)h->h_small.p, &n_unconv, pf));
     timed(pf, PTEBD_KERNEL_FINALIZE, stream, [&] { ptebd::launch_finalize<T>(d_jdesc, n, cutoff, lo, stream); });
@@ -723,9 +944,10 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   if (pf->on) {
     pf->harvest();
     const double ce = (double)sizeof(cplx<T>);
-    // executed Jacobi rows: a Gram matrix over r rows costs 6144 r flops and 32 r complex
-    // reads, a rotation of r rows (W's, plus V's) 8192 r flops and 64 r complex reads and
-    // writes
+    // executed Jacobi rows: with b-column blocks a pair's Gram matrix over r rows forms the
+    // upper 16 x 16 complex tiles of its 2b x 2b matrix, 3 (b = 16) or 10 (b = 32) tiles of
+    // 2048 r flops each, reading 2b r complex entries; a rotation of r rows (W's, plus V's)
+    // costs 8 (2b)^2 r flops and reads and writes 2b r complex entries each way
     const size_t wn = sizeof(uint32_t) * 2 * (size_t)n * L.nslot;
     PT_HIP(hipMemcpyAsync((char*)h->h_out.p + L.work, (char*)h->outbuf.p + L.work, wn,
                           hipMemcpyDeviceToHost, stream));
@@ -736,8 +958,10 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
       gram_rows += hw[2 * x];
       rot_rows += hw[2 * x + 1];
     }
-    pf->st[PTEBD_KERNEL_JACOBI].flops += 6144.0 * gram_rows + 8192.0 * rot_rows;
-    pf->st[PTEBD_KERNEL_JACOBI].bytes += ce * (32.0 * gram_rows + 64.0 * rot_rows);
+    const double bw = lo.block_cols;
+    const double tiles = bw == 32 ? 10.0 : 3.0;
+    pf->st[PTEBD_KERNEL_JACOBI].flops += 2048.0 * tiles * gram_rows + 32.0 * bw * bw * rot_rows;
+    pf->st[PTEBD_KERNEL_JACOBI].bytes += ce * (2.0 * bw * gram_rows + 4.0 * bw * rot_rows);
     for (int i = 0; i < n; ++i) {
       const GateDesc& d = descs[i];
       const double cl = d.cl, cm = d.cm, cr = d.cr, kk = hk[i];
@@ -864,7 +1088,7 @@ int jacobi_sweeps(hipStream_t stream, const GateDesc* d_desc, int n, int max_c,
                   const LayerOut& lo, int precision, int max_sweeps, double tol_factor,
                   int inner_sweeps, double inner_repeat, int sort_pairs, int32_t* h_counter,
                   int* n_unconverged) {
-  return run_jacobi<T>(stream, d_desc, n, max_c, lo, precision, max_sweeps, tol_factor,
+  return run_jacobi<T>(nullptr, stream, d_desc, n, max_c, lo, precision, max_sweeps, tol_factor,
                        inner_sweeps, inner_repeat, sort_pairs, h_counter, n_unconverged, nullptr);
 }
 
@@ -992,6 +1216,10 @@ int ptebd_mps_destroy(ptebd_mps_t h) {
   }
   if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  for (auto& evs : h->ev_sweep)
+    for (hipEvent_t e : evs)
+      if (e) (void)hipEventDestroy(e);
+  h->sweep_graphs.release();
   delete h;
   return PTEBD_OK;
 }
@@ -1006,6 +1234,8 @@ int ptebd_get_svd_params(ptebd_mps_t h, ptebd_svd_params* out) {
   out->sort_pairs = h->sort_pairs;
   out->precondition = h->precondition;
   out->streams = h->streams;
+  out->block_cols = h->block_cols;
+  out->graphs = h->graphs;
   return PTEBD_OK;
 }
 
@@ -1015,10 +1245,12 @@ int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* p) {
   if (p->max_sweeps < 1 || !(p->tol_factor > 0.0) || !std::isfinite(p->tol_factor) ||
       p->inner_sweeps < 1 || p->inner_sweeps > 64 || !(p->inner_repeat >= 0.0) ||
       !std::isfinite(p->inner_repeat) || (p->sort_pairs != 0 && p->sort_pairs != 1) ||
-      (p->precondition != 0 && p->precondition != 1) || (p->streams != 1 && p->streams != 2))
+      (p->precondition != 0 && p->precondition != 1) || (p->streams != 1 && p->streams != 2) ||
+      (p->block_cols != 16 && p->block_cols != 32) ||
+      (p->block_cols == 32 && h->precision != PTEBD_FP32) || (p->graphs != 0 && p->graphs != 1))
     return fail(PTEBD_EINVAL, "need max_sweeps >= 1, tol_factor > 0, inner_sweeps in [1, 64], "
-                              "finite inner_repeat >= 0, sort_pairs and precondition 0/1, "
-                              "streams 1 or 2");
+                              "finite inner_repeat >= 0, sort_pairs, precondition and graphs "
+                              "0/1, streams 1 or 2, block_cols 16 or (FP32 only) 32");
   h->max_sweeps = p->max_sweeps;
   h->tol_factor = p->tol_factor;
   h->inner_sweeps = p->inner_sweeps;
@@ -1026,6 +1258,8 @@ int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* p) {
   h->sort_pairs = p->sort_pairs;
   h->precondition = p->precondition;
   h->streams = p->streams;
+  h->block_cols = p->block_cols;
+  h->graphs = p->graphs;
   return PTEBD_OK;
 }
 
@@ -1706,7 +1940,8 @@ int svd_batched_t(int precision, int batch, int m, int n, const double* a, doubl
   const LayerOut lo = make_layer_out(outb.p, L, C);
   int32_t counter = 0;
   int n_unconv = 0;
-  int st = run_jacobi<T>(stream, (const GateDesc*)desc.p, batch, C, lo, precision, max_sweeps,
+  int st = run_jacobi<T>(nullptr, stream, (const GateDesc*)desc.p, batch, C, lo, precision,
+                         max_sweeps,
                          tol_factor, 1, 0.0, 1, &counter, &n_unconv, nullptr);
   if (st < 0) return cleanup(st);
   ptebd::launch_finalize<T>((const GateDesc*)desc.p, batch, 0.0, lo, stream);

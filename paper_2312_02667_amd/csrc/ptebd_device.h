@@ -147,6 +147,68 @@ __device__ inline void load4(bool ok, gptr<const cplx<T>> p, cplx<T> (&o)[4]) {
   }
 }
 
+// Round-robin (circle method) tournament: player in `slot` during `round`, for an even
+// number of players; slot 0 is fixed, the others rotate.  Pairs are (p, nplayers-1-p).
+__device__ inline int rr_player(int slot, int round, int nplayers) {
+  return slot == 0 ? 0 : 1 + ((slot - 1 + round) % (nplayers - 1));
+}
+
+// The same tournament for 32 players and round < 31, without an integer division.
+__device__ inline int rr32(int slot, int round) {
+  int x = slot - 1 + round;
+  x -= (x >= 31) ? 31 : 0;
+  return slot == 0 ? 0 : 1 + x;
+}
+
+// FP64 reciprocal square root for positive finite arguments: the hardware estimate (relative
+// error 2^-24 on gfx950, measured) refined by NEWTON Newton steps, each of which doubles the
+// number of correct bits: one step gives 2^-47, two give full double precision.
+template <int NEWTON>
+__device__ inline double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < NEWTON; ++i) y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
+// Jacobi rotation of the Hermitian 2x2 block [[a, g], [conj(g), b]] in FP64 (the symmetric
+// Schur step with the phase of g factored out): J = [[c, s], [-conj(s), c]] with
+// zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
+// s = t c g/|g|; J^H [[a, g], [conj g, b]] J is diagonal.  With d = |b - a| and
+// S = sqrt(d^2 + 4|g|^2) the same rotation is c = sqrt((d + S) / (2S)) and
+// s = sign(b - a) g sqrt(2 / (S (d + S))) (sign +1 for b = a), which takes one square root
+// and one reciprocal square root, no division, and stays finite for |g| far below |b - a|.
+// A block whose entries lie outside [1e-140, 1e140] is first scaled by 2^(+-600) (exact) so
+// that d^2 + 4|g|^2 stays a normal number.  Identity when |g| <= thr * sqrt(a b) or g = 0.
+// NEWTON: refinement steps of the reciprocal square roots (2 for rotations applied in FP64;
+// 1 is exact to 2^-47, ample for rotations rounded to FP32).
+template <int NEWTON>
+__device__ inline bool jacobi_rotation(double a, double b, double gr, double gi, double thr,
+                                       double& c, double& sr, double& si) {
+  const double g2 = gr * gr + gi * gi;
+  c = 1.0;
+  sr = 0.0;
+  si = 0.0;
+  if (!(g2 > 0.0) || g2 <= thr * thr * fmax(a * b, 0.0)) return false;
+  double d = fabs(b - a), xr = gr, xi = gi;
+  const double m = fmax(d, fmax(fabs(gr), fabs(gi)));
+  if (m < 1e-140 || m > 1e140) {
+    const double f = m < 1e-140 ? 0x1p600 : 0x1p-600;
+    d *= f;
+    xr *= f;
+    xi *= f;
+  }
+  const double dd = fma(d, d, 4.0 * (xr * xr + xi * xi));
+  const double S = dd * rsqrt_f64<NEWTON>(dd);
+  const double e = d + S;
+  const double sf = rsqrt_f64<NEWTON>(0.5 * S * e);
+  c = 0.5 * e * sf;
+  const double ss = b >= a ? sf : -sf;
+  sr = ss * xr;
+  si = ss * xi;
+  return true;
+}
+
 __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
   return v;

@@ -79,7 +79,9 @@ struct LayerOut {
                      // that start.
   int32_t nbmax;     // 16-column blocks of cmax
   int32_t triangular;  // 1: the Jacobi starts from a lower-triangular W (block b starts at
-                       // row 16 b), 0: every block starts at row 0
+                       // row block_cols * b), 0: every block starts at row 0
+  int32_t block_cols;  // columns per Jacobi block: 16 (jacobi_round_kernel) or 32
+                       // (jacobi64_round_kernel, FP32 only); rstart is indexed by block
   int32_t cmax;
 };
 
@@ -110,10 +112,19 @@ struct SampleSite {
 // Kernel launchers (ptebd_kernels.hip).  All are asynchronous on `stream`.
 template <class T>
 void launch_theta(const GateDesc* d_desc, int n_gates, int max_tiles, hipStream_t stream);
+// One round of a sweep; prev_slot >= 0: every workgroup returns at once when
+// out.counters[prev_slot] (the previous sweep's count of unconverged gates) is zero.
 template <class T>
 void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
                          const LayerOut& out, double tol_scale, int inner_sweeps,
-                         double inner_repeat, int sort_pairs, hipStream_t stream);
+                         double inner_repeat, int sort_pairs, int prev_slot,
+                         hipStream_t stream);
+// The same round with 32-column blocks (FP32 only; ptebd_jacobi64.hip); nbp counts 32-column
+// blocks.
+void launch_jacobi_round64(const GateDesc* d_desc, int n_gates, int round, int nbp,
+                           const LayerOut& out, double tol_scale, int inner_sweeps,
+                           double inner_repeat, int sort_pairs, int prev_slot,
+                           hipStream_t stream);
 void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
                         double unit_roundoff, const LayerOut& out, hipStream_t stream);
 template <class T>

@@ -13,68 +13,6 @@
 namespace ptebd {
 namespace {
 
-// Round-robin (circle method) tournament: player in `slot` during `round`, for an even
-// number of players; slot 0 is fixed, the others rotate.  Pairs are (p, nplayers-1-p).
-__device__ inline int rr_player(int slot, int round, int nplayers) {
-  return slot == 0 ? 0 : 1 + ((slot - 1 + round) % (nplayers - 1));
-}
-
-// The same tournament for 32 players and round < 31, without an integer division.
-__device__ inline int rr32(int slot, int round) {
-  int x = slot - 1 + round;
-  x -= (x >= 31) ? 31 : 0;
-  return slot == 0 ? 0 : 1 + x;
-}
-
-// FP64 reciprocal square root for positive finite arguments: the hardware estimate (relative
-// error 2^-24 on gfx950, measured) refined by NEWTON Newton steps, each of which doubles the
-// number of correct bits: one step gives 2^-47, two give full double precision.
-template <int NEWTON>
-__device__ inline double rsqrt_f64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int i = 0; i < NEWTON; ++i) y = y * (1.5 - 0.5 * x * y * y);
-  return y;
-}
-
-// Jacobi rotation of the Hermitian 2x2 block [[a, g], [conj(g), b]] in FP64 (the symmetric
-// Schur step with the phase of g factored out): J = [[c, s], [-conj(s), c]] with
-// zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2),
-// s = t c g/|g|; J^H [[a, g], [conj g, b]] J is diagonal.  With d = |b - a| and
-// S = sqrt(d^2 + 4|g|^2) the same rotation is c = sqrt((d + S) / (2S)) and
-// s = sign(b - a) g sqrt(2 / (S (d + S))) (sign +1 for b = a), which takes one square root
-// and one reciprocal square root, no division, and stays finite for |g| far below |b - a|.
-// A block whose entries lie outside [1e-140, 1e140] is first scaled by 2^(+-600) (exact) so
-// that d^2 + 4|g|^2 stays a normal number.  Identity when |g| <= thr * sqrt(a b) or g = 0.
-// NEWTON: refinement steps of the reciprocal square roots (2 for rotations applied in FP64;
-// 1 is exact to 2^-47, ample for rotations rounded to FP32).
-template <int NEWTON>
-__device__ inline bool jacobi_rotation(double a, double b, double gr, double gi, double thr,
-                                       double& c, double& sr, double& si) {
-  const double g2 = gr * gr + gi * gi;
-  c = 1.0;
-  sr = 0.0;
-  si = 0.0;
-  if (!(g2 > 0.0) || g2 <= thr * thr * fmax(a * b, 0.0)) return false;
-  double d = fabs(b - a), xr = gr, xi = gi;
-  const double m = fmax(d, fmax(fabs(gr), fabs(gi)));
-  if (m < 1e-140 || m > 1e140) {
-    const double f = m < 1e-140 ? 0x1p600 : 0x1p-600;
-    d *= f;
-    xr *= f;
-    xi *= f;
-  }
-  const double dd = fma(d, d, 4.0 * (xr * xr + xi * xi));
-  const double S = dd * rsqrt_f64<NEWTON>(dd);
-  const double e = d + S;
-  const double sf = rsqrt_f64<NEWTON>(0.5 * S * e);
-  c = 0.5 * e * sf;
-  const double ss = b >= a ? sf : -sf;
-  sr = ss * xr;
-  si = ss * xi;
-  return true;
-}
-
 // ---------------------------------------------------------------- theta
 // One workgroup computes a 32 (a) x 32 (c) tile of the four products
 // M_st = A_s B_t, A_s = diag(Lambda[q]) Gamma[q]_s diag(Lambda[q+1]) (chi_q x chi_{q+1}),
@@ -249,7 +187,7 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
     for (int i = threadIdx.x; i < 2 * out.nslot; i += blockDim.x)
       out.work[(size_t)g * 2 * out.nslot + i] = 0u;
     for (int b = threadIdx.x; b < out.nbmax; b += blockDim.x)
-      out.rstart[(size_t)g * out.nbmax + b] = out.triangular ? 16 * b : 0;
+      out.rstart[(size_t)g * out.nbmax + b] = out.triangular ? out.block_cols * b : 0;
     if (threadIdx.x == 0) {
       out.conv[g] = 0;
       out.sweeps[g] = 0;
@@ -287,7 +225,11 @@ template <class T>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kernel(const GateDesc* __restrict__ descs,
                                                            int round, int nbp, LayerOut out,
                                                            double tol_scale, int inner_sweeps,
-                                                           double inner_repeat, int sort_pairs) {
+                                                           double inner_repeat, int sort_pairs,
+                                                           int prev_slot) {
+  // the previous sweep left no gate of the batch unconverged (a sweep queued ahead of the
+  // host's convergence check): nothing to do
+  if (prev_slot >= 0 && out.counters[prev_slot] == 0) return;
   const int g = blockIdx.y;
   if (out.conv[g]) return;
   const GateDesc* d = descs + g;
@@ -1001,11 +943,12 @@ void launch_jacobi_init(const GateDesc* d_desc, int n_gates, int max_c, const La
 template <class T>
 void launch_jacobi_round(const GateDesc* d_desc, int n_gates, int round, int nbp,
                          const LayerOut& out, double tol_scale, int inner_sweeps,
-                         double inner_repeat,
-                         int sort_pairs, hipStream_t stream) {
+                         double inner_repeat, int sort_pairs, int prev_slot,
+                         hipStream_t stream) {
   if (n_gates <= 0 || nbp < 2) return;
   hipLaunchKernelGGL(jacobi_round_kernel<T>, dim3(nbp / 2, n_gates), dim3(256), 0, stream,
-                     d_desc, round, nbp, out, tol_scale, inner_sweeps, inner_repeat, sort_pairs);
+                     d_desc, round, nbp, out, tol_scale, inner_sweeps, inner_repeat, sort_pairs,
+                     prev_slot);
 }
 
 void launch_sweep_check(const GateDesc* d_desc, int n_gates, int sweep, double tol_factor,
@@ -1042,9 +985,9 @@ template void launch_theta<double>(const GateDesc*, int, int, hipStream_t);
 template void launch_jacobi_init<float>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
 template void launch_jacobi_init<double>(const GateDesc*, int, int, const LayerOut&, hipStream_t);
 template void launch_jacobi_round<float>(const GateDesc*, int, int, int, const LayerOut&, double,
-                                         int, double, int, hipStream_t);
+                                         int, double, int, int, hipStream_t);
 template void launch_jacobi_round<double>(const GateDesc*, int, int, int, const LayerOut&, double,
-                                          int, double, int, hipStream_t);
+                                          int, double, int, int, hipStream_t);
 template void launch_finalize<float>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
 template void launch_finalize<double>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
 template void launch_writeback<float>(const GateDesc*, int, const LayerOut&, hipStream_t);

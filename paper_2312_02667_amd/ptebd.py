@@ -58,7 +58,8 @@ class SvdParams(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int), ("tol_factor", ctypes.c_double),
                 ("inner_sweeps", ctypes.c_int), ("inner_repeat", ctypes.c_double),
                 ("sort_pairs", ctypes.c_int), ("precondition", ctypes.c_int),
-                ("streams", ctypes.c_int)]
+                ("streams", ctypes.c_int), ("block_cols", ctypes.c_int),
+                ("graphs", ctypes.c_int)]
 
 
 class KernelStats(ctypes.Structure):

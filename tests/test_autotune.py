@@ -7,8 +7,8 @@ import pytest
 
 from paper_2312_02667_amd import autotune
 
-DEFAULTS = {"inner_sweeps": 2, "inner_repeat": 1e-2, "sort_pairs": 1, "streams": 2,
-            "precondition": 1}
+DEFAULTS = {"block_cols": 16, "inner_sweeps": 2, "inner_repeat": 1e-2, "sort_pairs": 1,
+            "streams": 2, "precondition": 1}
 
 
 def test_cache_key_buckets():
@@ -26,14 +26,14 @@ def _separable(opt, weights=None):
     def evaluate(p):
         calls.append(dict(p))
         ms = 100.0 + sum((weights or {}).get(k, 5.0) * (p[k] != opt[k]) for k in opt)
-        return {"ms": ms, "ok": True, "lambda_dev": 0.0, "max_sweeps": 5}
+        return {"ms": ms, "ok": True, "err_F": 0.0, "max_sweeps": 5}
     return evaluate, calls
 
 
 def test_search_reaches_the_optimum_from_the_defaults():
     space = autotune._space_for("fp32")
-    opt = {"inner_sweeps": 3, "inner_repeat": 3e-2, "sort_pairs": 0, "streams": 1,
-           "precondition": 1}
+    opt = {"block_cols": 32, "inner_sweeps": 3, "inner_repeat": 3e-2, "sort_pairs": 0,
+           "streams": 1, "precondition": 1}
     evaluate, calls = _separable(opt)
     best, best_r, history = autotune.search(evaluate, DEFAULTS, space)
     assert best == opt
@@ -42,13 +42,25 @@ def test_search_reaches_the_optimum_from_the_defaults():
     assert len({tuple(sorted(c.items())) for c in calls}) == len(calls)  # no repeats
 
 
-def test_search_skips_fp64_preconditioning():
+def test_search_skips_fp64_preconditioning_and_wide_blocks():
     space = autotune._space_for("fp64")
-    assert "precondition" not in space
-    d = {k: v for k, v in DEFAULTS.items() if k != "precondition"}
+    assert "precondition" not in space and "block_cols" not in space
+    d = {k: v for k, v in DEFAULTS.items() if k not in ("precondition", "block_cols")}
     evaluate, calls = _separable({**d, "streams": 1})
     best, _, _ = autotune.search(evaluate, d, space)
-    assert best["streams"] == 1 and all("precondition" not in c for c in calls)
+    assert best["streams"] == 1
+    assert all("precondition" not in c and "block_cols" not in c for c in calls)
+
+
+def test_acceptance_uses_the_fidelity_budget():
+    """Converged, within ERR_F_TOL and within ERR_F_SLACK x the default's err_F."""
+    tol = autotune.ERR_F_TOL["fp32"]
+    assert autotune.accept(1e-9, 1e-9, "fp32", 0)
+    assert not autotune.accept(1e-9, 1e-9, "fp32", 1)               # an SVD hit the cap
+    assert not autotune.accept(2 * tol, 2 * tol, "fp32", 0)         # over the budget
+    assert not autotune.accept(5e-9, 1e-9, "fp32", 0)               # 5x the default's error
+    assert autotune.accept(3.9e-9, 1e-9, "fp32", 0)
+    assert autotune.accept(1e-14, 0.0, "fp64", 0)                   # FP64 overlap resolution
 
 
 def test_failed_candidates_are_never_chosen():
@@ -58,7 +70,7 @@ def test_failed_candidates_are_never_chosen():
         # the fastest schedule does not converge
         bad = p["inner_sweeps"] == 1
         return {"ms": 50.0 if bad else 100.0 - p["streams"], "ok": not bad,
-                "lambda_dev": 0.0, "max_sweeps": 30 if bad else 6}
+                "err_F": 0.0, "max_sweeps": 30 if bad else 6}
     best, best_r, _ = autotune.search(evaluate, DEFAULTS, space)
     assert best["inner_sweeps"] != 1 and best_r["ok"]
 
@@ -118,7 +130,7 @@ def test_noise_level_gains_do_not_move_the_schedule():
 
     def evaluate(p):
         # every other schedule 0.5 % faster than the defaults: below the 1 % threshold
-        return {"ms": 100.0 if p == DEFAULTS else 99.5, "ok": True, "lambda_dev": 0.0,
+        return {"ms": 100.0 if p == DEFAULTS else 99.5, "ok": True, "err_F": 0.0,
                 "max_sweeps": 6}
     best, _, _ = autotune.search(evaluate, DEFAULTS, space)
     assert best == DEFAULTS

@@ -11,38 +11,41 @@ from tests.gpu_util import lambda_diff, oracle_cutoff, say, to_oracle
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("precondition", [True, False])
-def test_mixed_path_against_oracle_at_chi_256(precondition):
+@pytest.mark.parametrize("precondition,block_cols", [(True, 16), (False, 16), (True, 32),
+                                                      (False, 32)])
+def test_mixed_path_against_oracle_at_chi_256(precondition, block_cols):
     """N = 40, depth 14, chi_max = 256, Haar SU(4): bulk bonds saturate (512x512 theta from
     layer 9); err_F of the FP32 path against the FP64 oracle must stay <= 1e-6, with the
-    preconditioned SVD (the default) and without it."""
+    preconditioned SVD (the default) and without it, with 16- and 32-column Jacobi blocks."""
     n, depth, chi = 40, 14, 256
     layers = inputs.brickwork_circuit(n, depth, seed=3)
     ref = po.product_state(n)
     m = ptebd.MPS(n, chi, "fp32")
-    m.set_svd_params(precondition=precondition)
+    m.set_svd_params(precondition=precondition, block_cols=block_cols)
     for li, (bonds, gates) in enumerate(layers):
         m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12)
         po.apply_layer(ref, bonds, gates, chi_max=chi, cutoff=oracle_cutoff(1e-12, "fp32"))
         if li + 1 >= 9:
             err = po.fidelity_error(ref, to_oracle(m))
-            say(f"precondition={precondition} layer {li + 1}: err_F(fp32 GPU vs FP64 oracle) = {err:.3e}")
+            say(f"precondition={precondition} block_cols={block_cols} layer {li + 1}: "
+                f"err_F(fp32 GPU vs FP64 oracle) = {err:.3e}")
             assert err <= 1e-6
     assert m.bond_dims() == ref.bond_dims()
     m.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision,block_cols", [("fp32", 16), ("fp32", 32), ("fp64", 16)])
 @pytest.mark.parametrize("chi", [20, 40, 100])
-def test_mixed_path_ragged_caps(precision, chi):
-    """Caps whose theta widths (2 chi = 40, 80, 200) are not multiples of the 16-column Jacobi
-    blocks or the 32-column preconditioner tiles, and give an odd block count (13 at
-    chi = 100): N = 30, depth 12, Haar SU(4), against the FP64 oracle (err_F and bond
-    dimensions after every layer from the first truncating one)."""
+def test_mixed_path_ragged_caps(precision, block_cols, chi):
+    """Caps whose theta widths (2 chi = 40, 80, 200) are not multiples of the 16- or 32-column
+    Jacobi blocks or the 32-column preconditioner tiles, and give odd block counts (13 at
+    chi = 100 with 16 columns, 7 with 32): N = 30, depth 12, Haar SU(4), against the FP64
+    oracle (err_F and bond dimensions after every layer from the first truncating one)."""
     n, depth = 30, 12
     layers = inputs.brickwork_circuit(n, depth, seed=11)
     ref = po.product_state(n)
     m = ptebd.MPS(n, chi, precision)
+    m.set_svd_params(block_cols=block_cols)
     bound = 1e-6 if precision == "fp32" else 1e-12
     for li, (bonds, gates) in enumerate(layers):
         st = m.apply_layer(bonds, gates, chi_max=chi, cutoff=1e-12)
@@ -56,8 +59,8 @@ def test_mixed_path_ragged_caps(precision, chi):
     m.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_two_streams_bit_identical(precision):
+@pytest.mark.parametrize("precision,block_cols", [("fp32", 16), ("fp32", 32), ("fp64", 16)])
+def test_two_streams_bit_identical(precision, block_cols):
     """A batch of >= 64 bond updates (a layer, or a PtSU half-step) runs as two halves on two
     streams by default; one stream must give bitwise the same state."""
     n, depth, chi = 200, 9, 32
@@ -65,7 +68,8 @@ def test_two_streams_bit_identical(precision):
     a = ptebd.MPS(n, chi, precision)
     b = ptebd.MPS(n, chi, precision)
     assert a.svd_params()["streams"] == 2
-    b.set_svd_params(streams=1)
+    a.set_svd_params(block_cols=block_cols)
+    b.set_svd_params(streams=1, block_cols=block_cols)
     for bonds, gates in layers:
         sa = a.apply_layer(bonds, gates, chi_max=chi)
         sb = b.apply_layer(bonds, gates, chi_max=chi)
@@ -77,6 +81,44 @@ def test_two_streams_bit_identical(precision):
         sb = b.apply_layer(bonds, gates, chi_max=chi, ptsu_steps=2)
         assert sa["triggered"] and sa["ptsu_done"] == 2 and sb["ptsu_done"] == 2
         assert np.array_equal(sa["sweeps"], sb["sweeps"])
+    ga, la = a.export()
+    gb, lb = b.export()
+    assert all(np.array_equal(x, y) for x, y in zip(la, lb))
+    assert all(np.array_equal(x, y) for x, y in zip(ga, gb))
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision,block_cols,streams", [("fp32", 16, 2), ("fp32", 32, 1),
+                                                         ("fp64", 16, 2), ("fp64", 16, 1)])
+def test_graph_sweeps_bit_identical_to_eager_sweeps(precision, block_cols, streams):
+    """Each Jacobi sweep as one launch of a captured graph (the default) against the same
+    sweeps launched kernel by kernel: bitwise the same states and sweep counts over layers
+    that replay the cached graphs (with other work and host synchronization in between),
+    change the batch shape (PtSU half-steps, growing bond dimensions) and hit the sweep cap."""
+    n, chi = 200, 32
+    layers = inputs.brickwork_circuit(n, 10, seed=25)
+    a = ptebd.MPS(n, chi, precision)
+    b = ptebd.MPS(n, chi, precision)
+    a.set_svd_params(block_cols=block_cols, streams=streams)
+    b.set_svd_params(block_cols=block_cols, streams=streams, graphs=0)
+    assert a.svd_params()["graphs"] == 1
+    for li, (bonds, gates) in enumerate(layers):
+        say(f"graphs vs eager {precision} b{block_cols} s{streams} layer {li + 1}")
+        ptsu = 1 if li >= 7 else 0
+        sa = a.apply_layer(bonds, gates, chi_max=chi, ptsu_steps=ptsu)
+        sb = b.apply_layer(bonds, gates, chi_max=chi, ptsu_steps=ptsu)
+        assert np.array_equal(sa["sweeps"], sb["sweeps"])
+        assert sa["max_sweeps"] == sb["max_sweeps"] and sa["ptsu_done"] == sb["ptsu_done"]
+        assert abs(a.norm() - b.norm()) == 0.0           # eager queries between replays
+    for m in (a, b):
+        m.set_svd_params(max_sweeps=2)
+    for bonds, gates in inputs.brickwork_circuit(n, 2, seed=26):
+        sa = a.apply_layer(bonds, gates, chi_max=chi)
+        sb = b.apply_layer(bonds, gates, chi_max=chi)
+        assert sa["status"] == sb["status"] == ptebd.WNOCONV
+        assert sa["n_unconverged"] == sb["n_unconverged"] > 0
+        assert int(np.max(sa["sweeps"])) == 2 and np.array_equal(sa["sweeps"], sb["sweeps"])
     ga, la = a.export()
     gb, lb = b.export()
     assert all(np.array_equal(x, y) for x, y in zip(la, lb))

@@ -202,13 +202,15 @@ def test_svd_params_round_trip_and_validation():
     m = ptebd.MPS(6, 8, "fp32")
     p = m.svd_params()
     assert p == {"max_sweeps": 30, "tol_factor": 1.0, "inner_sweeps": 2, "inner_repeat": 1e-2,
-                 "sort_pairs": 1, "precondition": 1, "streams": 2}
+                 "sort_pairs": 1, "precondition": 1, "streams": 2, "block_cols": 16,
+                 "graphs": 1}
     m.set_svd_params(inner_sweeps=3, inner_repeat=0.0, precondition=False)
     q = m.svd_params()
     assert q["inner_sweeps"] == 3 and q["inner_repeat"] == 0.0 and q["precondition"] == 0
     for bad in (dict(max_sweeps=0), dict(tol_factor=-1.0), dict(inner_sweeps=65),
                 dict(inner_repeat=-1.0), dict(inner_repeat=float("inf")), dict(sort_pairs=2),
-                dict(precondition=3), dict(streams=0), dict(streams=3)):
+                dict(precondition=3), dict(streams=0), dict(streams=3), dict(block_cols=24),
+                dict(graphs=2)):
         with pytest.raises(ptebd.PtebdError):
             m.set_svd_params(**bad)
         assert m.svd_params() == q          # nothing changed
@@ -218,6 +220,8 @@ def test_svd_params_round_trip_and_validation():
     d = ptebd.MPS(6, 8, "fp64")
     assert d.svd_params()["inner_sweeps"] == 1 and d.svd_params()["inner_repeat"] == 0.0
     assert d.svd_params()["tol_factor"] == 4.0
+    with pytest.raises(ptebd.PtebdError):
+        d.set_svd_params(block_cols=32)      # 32-column blocks: FP32 handles only
     d.close()
 
 
