@@ -200,6 +200,12 @@ int ptebd_set_svd_params(ptebd_mps_t h, const ptebd_svd_params* params);
  * the layer on the handle's stream and returns after it has completed (the new bond
  * dimensions are read back to size the next layer).
  * Errors: EINVAL, EOVERLAP, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV.
+ * The gate layer and each PtSU half-step after it are batches that commit as a whole: the
+ * host checks every gate's ENONFINITE / EANNIHILATED flag before anything of the state is
+ * written, so a batch that fails leaves Gamma, Lambda, the bond dimensions and the norm and
+ * fidelity estimates as they were before it (an error in the layer leaves the state as it
+ * was before the call; one in a PtSU half-step leaves the layer and the earlier half-steps
+ * applied).  EINVAL and EOVERLAP are found before any device work.
  */
 int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
                       const int32_t* bonds, const double* gates, int chi_max, double cutoff,
@@ -217,7 +223,9 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
  * FP32 floor applies).  norm_out (may be NULL) receives n.  The 2N-3 bond updates run in
  * about N sequential batches: the cost is sequential in N, unlike a layer.  The norm and
  * fidelity estimates are left unchanged.
- * Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV. */
+ * Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV.  Each batch
+ * of tSU steps commits as a whole (see ptebd_apply_layer); after an error the state holds the
+ * batches done so far, which change its gauge but not the wavefunction beyond the cutoff. */
 int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out);
 
 /* Perfect sampling of n_samples bit strings from state s, which must be in canonical form
@@ -240,7 +248,7 @@ int ptebd_sample(ptebd_mps_t h, int s, int n_samples, const double* uniforms, ui
  * of Sec. II.C with the identity gate skipped (the shortcut noted in Sec. III.D), cutoff only
  * (no chi bound), nu = 1.  It leaves the state unchanged up to rounding and the cutoff.
  * steps >= 0, cutoff in [0, 1).  Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED;
- * warning WNOCONV. */
+ * warning WNOCONV.  Each half-step commits as a whole (see ptebd_apply_layer). */
 int ptebd_ptsu(ptebd_mps_t h, int s, int steps, double cutoff);
 
 /* Exact norm n = sqrt(<Psi|Psi>) of state s (the quantity whose decay Sec. III.C.1 studies)

@@ -644,15 +644,16 @@ const SplitStreams* split_for(ptebd_mps* h, int n, const OutLayout& L, SplitStre
 }
 
 // A large batch as two independent pipelines: gates [0, n/2) on `stream`, [n/2, n) on the
-// second stream, each running theta, the preconditioning, its own Jacobi sweeps, finalize,
-// the recovery and the write-back.  The host advances each half's sweeps as soon as its
+// second stream, each running theta, the preconditioning, its own Jacobi sweeps, finalize
+// and the recovery (the write-back follows for the whole batch once its errors have been
+// checked).  The host advances each half's sweeps as soon as its
 // own convergence counter is read, so one half's theta and preconditioning, sweep
 // boundaries and last launches overlap the other half's rounds.  Jacobi time is the union
 // of the intervals in which either half's rounds ran (events on one clock), each round over
 // half the gates counting as half a launch.  Both streams have drained on return.
 template <class T>
 int run_split(ptebd_mps* h, const SplitStreams& sp, const GateDesc* d_desc,
-              const GateDesc* d_jdesc, const GateDesc* d_wdesc, int n, int max_c, int max_r,
+              const GateDesc* d_jdesc, int n, int max_c, int max_r,
               int max_tiles, bool pre, double cutoff, const LayerOut& lo,
               const ptebd::PrecondOut& po, int32_t* h_counter, int* n_unconverged) {
   hipStream_t stream = h->stream;
@@ -705,13 +706,10 @@ int run_split(ptebd_mps* h, const SplitStreams& sp, const GateDesc* d_desc,
       PT_CHECK(timed_span(pf, PTEBD_KERNEL_PRECOND, st[k], 0.0, [&] {
         ptebd::launch_recover(d_desc + off[k], jd, nn[k], max_r, max_c, pp[k], oo[k], st[k]);
       }));
-    PT_CHECK(timed_span(pf, PTEBD_KERNEL_WRITEBACK, st[k], 0.5, [&] {
-      ptebd::launch_writeback<T>(d_wdesc + off[k], nn[k], oo[k], st[k]);
-    }));
     return PTEBD_OK;
   };
   // each half's sweeps run device-driven (SweepDriver); the host serves whichever half's
-  // next count is due, queueing that half's next sweep or its finalize and write-back
+  // next count is due, queueing that half's next sweep or its finalize and recovery
   SweepDriver<T> drv[2] = {
       {h->graphs ? &h->sweep_graphs : nullptr, st[0],
        SweepArgs{d_jdesc, nn[0], nbp, oo[0], h->tol_factor, u, h->inner_sweeps,
@@ -876,7 +874,7 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
   SplitStreams sp;
   const SplitStreams* split = split_for(h, n, L, &sp);
   if (split) {
-    PT_CHECK(run_split<T>(h, *split, d_desc, d_jdesc, d_wdesc, n, max_c, max_r, max_tiles, pre,
+    PT_CHECK(run_split<T>(h, *split, d_desc, d_jdesc, n, max_c, max_r, max_tiles, pre,
                           cutoff, lo, po, (int32_t*)h->h_small.p, &n_unconv));
   } else {
     timed(pf, PTEBD_KERNEL_THETA, stream, [&] { ptebd::launch_theta<T>(d_desc, n, max_tiles, stream); });
@@ -897,7 +895,6 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
       timed(pf, PTEBD_KERNEL_PRECOND, stream, [&] {
         ptebd::launch_recover(d_desc, d_jdesc, n, max_r, max_c, po, lo, stream);
       });
-    timed(pf, PTEBD_KERNEL_WRITEBACK, stream, [&] { ptebd::launch_writeback<T>(d_wdesc, n, lo, stream); });
     PT_HIP(hipGetLastError());
   }
   // copy back the small per-gate outputs (k .. counters are contiguous after perm)
@@ -917,20 +914,26 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
     PT_HIP(hipMemcpy(c2, (char*)h->outbuf.p + L.counters2, sizeof(c2), hipMemcpyDeviceToHost));
     hc[2] |= c2[2];
   }
+  // Nothing of the state has been written so far: a batch with an error returns here and
+  // leaves Gamma, Lambda and the bond dimensions as they were.
+  if (hc[2] & 1) return fail(PTEBD_EANNIHILATED, "a two-site wavefunction vanished or eps >= 1");
+  if (hc[2] & 2) return fail(PTEBD_ENONFINITE, "non-finite singular value, eps or nu produced");
   // Algorithm 1 compresses a state's layer (nu, then PtSU) only when some of its gates had
-  // r > chi; the finalize kernels left Lambda[q+1] = sigma[:k], and nu multiplies it for the
-  // gates of such states only.
+  // r > chi; the write-back sets Lambda[q+1] = nu sigma[:k] for the gates of such states and
+  // sigma[:k] for the others.
   std::vector<char> trig(h->st.size(), 0);
   if (stabilize)
     for (int i = 0; i < n; ++i)
       if (items[i].chi > 0 && hr[i] > items[i].chi) trig[items[i].s] = 1;
   int32_t* happ = (int32_t*)h->h_gates.p;  // the gates' staging is free again
   for (int i = 0; i < n; ++i) happ[i] = trig[items[i].s] ? 1 : 0;
-  if (stabilize) {
+  if (stabilize)
     PT_HIP(hipMemcpyAsync(h->gates.p, happ, sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
-    ptebd::launch_apply_nu(d_desc, n, (const int32_t*)h->gates.p, lo, stream);
-    PT_HIP(hipGetLastError());
-  }
+  const int32_t* d_apply = stabilize ? (const int32_t*)h->gates.p : nullptr;
+  timed(pf, PTEBD_KERNEL_WRITEBACK, stream,
+        [&] { ptebd::launch_writeback<T>(d_wdesc, n, d_apply, lo, stream); });
+  PT_HIP(hipGetLastError());
+  PT_HIP(hipStreamSynchronize(stream));
   for (int i = 0; i < n; ++i) {
     res->k[i] = hk[i];
     res->r[i] = hr[i];
@@ -977,8 +980,6 @@ int run_updates(ptebd_mps* h, const std::vector<Item>& items, double cutoff,
       }
     }
   }
-  if (hc[2] & 1) return fail(PTEBD_EANNIHILATED, "a two-site wavefunction vanished or eps >= 1");
-  if (hc[2] & 2) return fail(PTEBD_ENONFINITE, "non-finite singular value, eps or nu produced");
   return PTEBD_OK;
 }
 

@@ -133,12 +133,11 @@ void launch_jacobi_init(const GateDesc* d_desc, int n_gates, int max_c, const La
 template <class T>
 void launch_finalize(const GateDesc* d_desc, int n_gates, double cutoff, const LayerOut& out,
                      hipStream_t stream);
+// Gamma[q], Gamma[q+1] and Lambda[q+1] of every gate: Lambda[q+1] = nu sigma[:k] for the
+// gates with d_apply[g] != 0 (d_apply may be nullptr: none), sigma[:k] for the others.
 template <class T>
-void launch_writeback(const GateDesc* d_desc, int n_gates, const LayerOut& out,
-                      hipStream_t stream);
-// Lambda[q+1] *= nu for the gates with d_apply[g] != 0; out.nu[g] = 1 for the others.
-void launch_apply_nu(const GateDesc* d_desc, int n_gates, const int32_t* d_apply,
-                     const LayerOut& out, hipStream_t stream);
+void launch_writeback(const GateDesc* d_desc, int n_gates, const int32_t* d_apply,
+                      const LayerOut& out, hipStream_t stream);
 
 // Preconditioned SVD of the FP32 path (ptebd_precond.hip).  d_desc: the theta descriptors
 // (w = theta, gram, left set); d_jdesc: the Jacobi descriptors (w = X, v = nullptr, R = C,

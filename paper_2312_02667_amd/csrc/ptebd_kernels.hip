@@ -4,7 +4,8 @@
 //                       column updates, FP64 inner rotations
 //   finalize_kernel  -- singular values, sort, truncation and discarded weight (Sec. III.B,
 //                       Theorem 1), norm stabilization nu (Sec. III.C.2, Eq. (lren))
-//   writeback_kernel -- Vidal regauge with Lambda^{-1} (Sec. II.C) into the state arena
+//   writeback_kernel -- Vidal regauge with Lambda^{-1} (Sec. II.C) and the new Lambda
+//                       (times nu on compressed layers) into the state arena
 #include <type_traits>
 
 #include "ptebd_device.h"
@@ -726,9 +727,10 @@ __global__ void sweep_check_kernel(const GateDesc* __restrict__ descs, int n_gat
 // ---------------------------------------------------------------- finalize
 // sigma_j = |W_j| (FP64), descending sort with the column permutation, r = #{sigma >
 // cutoff sigma_1}, k = min(chi_max, r), eps = sum_{j >= k} sigma_j^2, nu = (1-eps)^(-1/2),
-// Lambda[q+1] = sigma[:k].  Whether nu multiplies Lambda[q+1] depends on the whole layer
-// (Algorithm 1 compresses only when some bond exceeded chi), so apply_nu_kernel does that
-// once every gate of the batch has been finalized.
+// and the batch's error word.  The state is not written here: whether nu multiplies
+// Lambda[q+1] depends on the whole layer (Algorithm 1 compresses only when some bond
+// exceeded chi), and a batch with an error must leave the state as it was, so the
+// write-back sets Lambda[q+1] once every gate has been finalized and checked.
 template <class T>
 __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restrict__ descs,
                                                        double cutoff, LayerOut out) {
@@ -810,12 +812,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
   if (d->eps_mode == 1) eps = discarded / total;
   if (d->eps_mode == 2) eps = 1.0 - (total - discarded);
   const double nu = d->stabilize ? 1.0 / sqrt(1.0 - eps) : 1.0;
-  const gptr<double> lam_m = as_global(d->lam_m);
   for (int j = tid; j < C; j += 256) {
-    const double s = sqrt(fmax(key[j], 0.0));
-    out.sig[(size_t)g * out.cmax + j] = s;
+    out.sig[(size_t)g * out.cmax + j] = sqrt(fmax(key[j], 0.0));
     out.perm[(size_t)g * out.cmax + j] = idx[j];
-    if (lam_m != nullptr && j < k) lam_m[j] = s;
   }
   if (tid == 0) {
     out.k[g] = k;
@@ -829,30 +828,18 @@ __global__ __launch_bounds__(256) void finalize_kernel(const GateDesc* __restric
   }
 }
 
-// Norm stabilization of a compressed layer (Sec. III.C.2, Eq. (lren)): Lambda[q+1] <- nu
-// Lambda[q+1] for the gates whose state's layer was compressed (apply[g] != 0); the others
-// keep their singular values and report nu = 1.
-__global__ __launch_bounds__(256) void apply_nu_kernel(const GateDesc* __restrict__ descs,
-                                                       const int32_t* __restrict__ apply,
-                                                       LayerOut out) {
-  const int g = blockIdx.x;
-  const gptr<double> lam_m = as_global(descs[g].lam_m);
-  if (!apply[g]) {
-    if (threadIdx.x == 0) out.nu[g] = 1.0;
-    return;
-  }
-  const double nu = out.nu[g];
-  const int k = out.k[g];
-  for (int j = threadIdx.x; j < k; j += blockDim.x) lam_m[j] = nu * lam_m[j];
-}
-
 // ---------------------------------------------------------------- write-back
 // Gamma[q][a, s', j] = X[(s',a), j] / Lambda[q]_a and
 // Gamma[q+1][j, t', c] = Ydag[j, (t',c)] / Lambda[q+2]_c for the k kept columns, where
 // X = W/sigma, Ydag = V^H (W = theta) or X = V, Ydag = (W/sigma)^H (W = theta^H).
-// blockIdx.z = 0 writes Gamma[q], 1 writes Gamma[q+1] (LDS-transposed 32x32 tiles).
+// blockIdx.z = 0 writes Gamma[q], 1 writes Gamma[q+1] (LDS-transposed 32x32 tiles).  Block
+// (0, g, 0) also writes Lambda[q+1] = nu sigma[:k] where apply[g] != 0 (the state's layer
+// was compressed: norm stabilization, Sec. III.C.2, Eq. (lren)), else sigma[:k].  This is
+// the only kernel of a batch that writes the state: the host launches it once the batch's
+// error word is clear, so a batch either commits every gate or leaves the state untouched.
 template <class T>
 __global__ __launch_bounds__(256) void writeback_kernel(const GateDesc* __restrict__ descs,
+                                                        const int32_t* __restrict__ apply,
                                                         LayerOut out) {
   const int g = blockIdx.y;
   const GateDesc* d = descs + g;
@@ -863,6 +850,11 @@ __global__ __launch_bounds__(256) void writeback_kernel(const GateDesc* __restri
   const gptr<const cplx<T>> __restrict__ W = as_global((const cplx<T>*)d->w);
   const gptr<const cplx<T>> __restrict__ V = as_global((const cplx<T>*)d->v);
   const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && blockIdx.z == 0 && d->lam_m != nullptr) {
+    const double nu = (apply != nullptr && apply[g] != 0) ? out.nu[g] : 1.0;
+    const gptr<double> lam_m = as_global(d->lam_m);
+    for (int j = tid; j < k; j += 256) lam_m[j] = nu * sig[j];
+  }
   if (blockIdx.z == 0) {
     const gptr<const cplx<T>> __restrict__ L = transposed ? V : W;
     const int ldl = transposed ? C : R;
@@ -966,18 +958,12 @@ void launch_finalize(const GateDesc* d_desc, int n_gates, double cutoff, const L
                      out);
 }
 
-void launch_apply_nu(const GateDesc* d_desc, int n_gates, const int32_t* d_apply,
-                     const LayerOut& out, hipStream_t stream) {
-  if (n_gates <= 0) return;
-  hipLaunchKernelGGL(apply_nu_kernel, dim3(n_gates), dim3(256), 0, stream, d_desc, d_apply, out);
-}
-
 template <class T>
-void launch_writeback(const GateDesc* d_desc, int n_gates, const LayerOut& out,
-                      hipStream_t stream) {
+void launch_writeback(const GateDesc* d_desc, int n_gates, const int32_t* d_apply,
+                      const LayerOut& out, hipStream_t stream) {
   if (n_gates <= 0) return;
   hipLaunchKernelGGL(writeback_kernel<T>, dim3(64, n_gates, 2), dim3(256), 0, stream, d_desc,
-                     out);
+                     d_apply, out);
 }
 
 template void launch_theta<float>(const GateDesc*, int, int, hipStream_t);
@@ -990,7 +976,9 @@ template void launch_jacobi_round<double>(const GateDesc*, int, int, int, const 
                                           int, double, int, int, hipStream_t);
 template void launch_finalize<float>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
 template void launch_finalize<double>(const GateDesc*, int, double, const LayerOut&, hipStream_t);
-template void launch_writeback<float>(const GateDesc*, int, const LayerOut&, hipStream_t);
-template void launch_writeback<double>(const GateDesc*, int, const LayerOut&, hipStream_t);
+template void launch_writeback<float>(const GateDesc*, int, const int32_t*, const LayerOut&,
+                                      hipStream_t);
+template void launch_writeback<double>(const GateDesc*, int, const int32_t*, const LayerOut&,
+                                       hipStream_t);
 
 }  // namespace ptebd

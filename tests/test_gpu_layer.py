@@ -181,6 +181,47 @@ def test_layer_errors_leave_state_unchanged():
     m.close()
 
 
+@pytest.mark.parametrize("precision,n,scaled", [("fp32", 8, 4), ("fp64", 8, 4), ("fp32", 130, 100)])
+def test_device_error_leaves_state_unchanged(precision, n, scaled):
+    """An error found on the device commits nothing.  Lambda[scaled] is multiplied by 10, so
+    the gate at q = scaled - 1 sees sum sigma^2 near 100 and, cut to chi = 2 under the literal
+    reading, a discarded weight above 1 (EANNIHILATED: nu = (1 - eps)^(-1/2) does not exist,
+    Eq. (lren)).  That is known only after theta, the SVD and the truncation have run for
+    every gate of the layer; Gamma, Lambda, the bond dimensions and the estimates must still
+    be bit-identical afterwards.  At n = 130 the odd layer has 64 gates and runs as two
+    halves on two streams, and the failing gate sits in the second half.  The handle keeps
+    working: the same layer without truncation then matches the oracle."""
+    chi = 16 if n == 8 else 8
+    layers = inputs.brickwork_circuit(n, 6, seed=5)
+    m = ptebd.MPS(n, chi, precision)
+    for bonds, gates in layers:
+        m.apply_layer(bonds, gates, chi_max=chi)
+    ref = to_oracle(m)
+    lam = [x.copy() for x in ref.lam]
+    lam[scaled] = lam[scaled] * 10.0
+    m.import_state(ref.gam, lam)
+    before, dims = to_oracle(m), m.bond_dims()
+    est = (m.norm_estimate(), m.fidelity_estimate())
+    bonds, gates = layers[1]
+    assert scaled - 1 in list(bonds)
+    with pytest.raises(ptebd.PtebdError) as ei:
+        m.apply_layer(bonds, gates, chi_max=2)
+    assert ei.value.code == ptebd.EANNIHILATED
+    after = to_oracle(m)
+    assert m.bond_dims() == dims
+    assert (m.norm_estimate(), m.fidelity_estimate()) == est
+    for x, y in zip(before.lam, after.lam):
+        assert np.array_equal(x, y)
+    for x, y in zip(before.gam, after.gam):
+        assert np.array_equal(x, y)
+    m.apply_layer(bonds, gates, chi_max=chi, stabilize=False)
+    po.apply_layer(before, bonds, gates, chi_max=chi, cutoff=oracle_cutoff(1e-12, precision),
+                   stabilize=False)
+    scale = max(float(np.max(x)) for x in before.lam)
+    assert lambda_diff(before, to_oracle(m)) <= (1e-4 if precision == "fp32" else 1e-10) * scale
+    m.close()
+
+
 def test_kernel_profiling_counts_launches():
     n = 16
     layers = inputs.brickwork_circuit(n, 6, seed=2)
