@@ -150,13 +150,13 @@ class Path:
 def measured_traffic(kernel_name: str, precision: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, valid only while the kernel source is the one the counters were taken on."""
-    import hashlib
     import re
+
+    from paper_2312_02667_amd.trace_summary import kernel_source_digest
     summary = os.path.join(ROOT, "profiles", f"{kernel_name}_{precision}_N1024_chi256.md")
-    src = os.path.join(ROOT, "paper_2312_02667_amd", "csrc", "ptebd_kernels.hip")
     try:
         text = open(summary).read()
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        digest = kernel_source_digest()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
@@ -383,19 +383,16 @@ def main(argv=None):
     ptebd.set_device(0)
     stream = ptebd.default_stream()
     if args.copy_calibration > 0:
-        # an elementwise kernel that reads MIB MiB and writes MIB MiB (dst = 2 * src); torch
-        # runs it on its own HIP runtime, which is all a hardware counter calibration needs
-        import torch
+        # hbm_copy_kernel reads MIB MiB and writes MIB MiB per dispatch: the reference that
+        # fixes the unit of the HBM byte counters in the same profiler pass
+        import ctypes
 
-        n_el = args.copy_calibration * (1 << 20) // 4
-        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 x {args.copy_calibration} MiB read + write (torch.mul)")
-        del src, dst
+        copy_lib = ctypes.CDLL(os.path.join(ROOT, "paper_2312_02667_amd", "libhbmcopy.so"))
+        rc = copy_lib.hbm_copy_run(ctypes.c_int(args.copy_calibration), ctypes.c_int(3))
+        if rc != 0:
+            print(f"copy calibration failed ({rc})", file=sys.stderr)
+            return 1
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB read + write (hbm_copy_kernel)")
     chi, n = args.chi, args.n_sites
     n_setup = setup_layers(chi)
     if DEPTH <= n_setup:

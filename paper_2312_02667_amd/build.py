@@ -1,4 +1,5 @@
-"""Build libptebd.so for gfx950 with hipcc (in-tree, next to this file).
+"""Build libptebd.so (and the counter-calibration copy, libhbmcopy.so) for gfx950 with hipcc
+(in-tree, next to this file).
 
 Usage: ``python -m paper_2312_02667_amd.build`` or ``paper_2312_02667_amd.build.build()``.
 Every HIP source is compiled with packed FP32 instructions disabled
@@ -17,6 +18,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libptebd.so")
+# the copy of known size that calibrates the HBM byte counters (measurement support only)
+COPY_LIB = os.path.join(HERE, "libhbmcopy.so")
+COPY_SOURCE = "hbm_copy.hip"
 SOURCES = ["ptebd_api.hip", "ptebd_kernels.hip", "ptebd_queries.hip", "ptebd_sample.hip",
            "ptebd_precond.hip", "ptebd_noalloc.hip", "ptebd_jacobi64.hip"]
 ARCH = "gfx950"
@@ -56,6 +60,9 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    tmp = COPY_LIB + ".tmp"
+    _run([HIPCC, *COMMON, "-shared", "-o", tmp, os.path.join(CSRC, COPY_SOURCE)])
+    os.replace(tmp, COPY_LIB)
     return LIB
 
 
