@@ -4,7 +4,8 @@
 //   colsort_kernel   -- column norms of W in FP64 and a permutation ps sorting them in
 //                       descending order (A = W P, A[:, i] = W[:, ps[i]])
 //   gram64_kernel    -- G = A^H A in FP64 on MFMA (upper 32x32 tiles)
-//   potrf / trsm / herk_kernel -- blocked Cholesky G = R^H R (R upper), in place, FP64;
+//   potrf / trsm / herk_kernel -- blocked Cholesky G = R^H R (R upper), in place, FP64,
+//                       with trailing updates deferred over groups of four panels;
 //                       a pivot at or below 1e-13 G_00 marks a numerically dependent column
 //                       (its row of R is set to zero)
 //   xinit_kernel     -- X = R^H in FP32: the one-sided Jacobi then runs on X instead of W
@@ -161,9 +162,10 @@ __global__ __launch_bounds__(256) void gram64_kernel(const GateDesc* __restrict_
 
 // ---------------------------------------------------------------- blocked Cholesky
 // G = R^H R with R upper triangular, overwriting the upper triangle of G, 32 columns per
-// block step kb: potrf factors the diagonal block, trsm solves the block row
-// R[kb, j] = R[kb, kb]^{-H} G[kb, j], herk updates the trailing upper tiles
-// G[i, j] -= R[kb, i]^H R[kb, j].  A pivot d <= 1e-13 * G_00 (G_00 the largest column
+// block step kb: herk brings the block row kb up to date, potrf factors the diagonal
+// block, trsm solves the block row R[kb, j] = R[kb, kb]^{-H} G[kb, j], and after every
+// fourth panel herk updates the trailing upper tiles G[i, j] -= R[l, i]^H R[l, j] with the
+// group's rows l.  A pivot d <= 1e-13 * G_00 (G_00 the largest column
 // norm^2, the columns being sorted) is a numerically dependent column: its row of R is zero.
 constexpr double kPivotTol = 1e-13;
 
@@ -313,46 +315,44 @@ __global__ __launch_bounds__(256) void trsm_kernel(const GateDesc* __restrict__ 
   }
 }
 
-// Trailing update of the upper tiles (ti, tj), kb < ti <= tj: G -= R[kb, ti]^H R[kb, tj].
-// The two 32 x 32 blocks of R's block row and the output tile are staged through LDS with
-// coalesced column reads (G is column-major); four waves, each a 16 x 16 sub-tile on FP64
-// MFMA, subtract their products in LDS, and the tile is written back by columns.
-__global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ descs,
-                                                   int kb) {
+// Deferred updates of the blocked Cholesky: G[ti, tj] -= sum_l R[l, ti]^H R[l, tj] over the
+// rows l in [32 l0, 32 l1) of R, which the earlier panels left in the upper triangle of G.
+// mode 0: the block row ti = kb, tiles tj = kb + blockIdx.x, before panel kb is factored
+// (the rows of the panels since the last trailing update); mode 1: the upper tiles
+// kb < ti <= tj once panel kb has closed a group (a rank 32 (l1 - l0) trailing update).
+// Every operand entry has l < ti * 32 <= column, so it lies in the strict upper triangle,
+// and no tile written here is read by the same launch.  Four waves, each a 16 x 16
+// sub-tile on FP64 MFMA; K in steps of 16 rows with the next step's loads in flight,
+// operands straight from global memory (column-major G: a column's rows are contiguous).
+__global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ descs, int kb,
+                                                   int l0, int l1, int mode) {
   const int g = blockIdx.y;
   const int C = descs[g].C;
   const int nt = (C + 31) >> 5;
-  const int nrem = nt - kb - 1;
-  if (nrem <= 0 || (int)blockIdx.x >= nrem * (nrem + 1) / 2) return;
   int ti, tj;
-  tile_of(blockIdx.x, nrem, ti, tj);
-  ti += kb + 1;
-  tj += kb + 1;
-  z64* __restrict__ G = (z64*)descs[g].gram;
-  const int b0 = kb * 32;
-  const int nb = min(32, C - b0);
-  const int r0 = ti * 32, q0 = tj * 32;
-  const int ni = min(32, C - r0), nj = min(32, C - q0);
-  __shared__ z64 A[32][33];   // A[l][c] = R[b0 + l, r0 + c]
-  __shared__ z64 B[32][33];   // B[l][c] = R[b0 + l, q0 + c]
-  __shared__ z64 Gt[32][33];  // Gt[i][j] = G[r0 + i, q0 + j]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // unconditional loads from a clamped index (every matrix here has C <= 1024, so 32-bit
-  // element offsets), masked to zero outside the tile
-  const gptr<const z64> Gg = as_global((const z64*)G);
-  for (int e = tid; e < 1024; e += 256) {
-    const int l = e & 31, c = e >> 5;
-    const bool oka = l < nb && c < ni, okb = l < nb && c < nj, okg = l < ni && c < nj;
-    const uint32_t ia = oka ? (uint32_t)(r0 + c) * (uint32_t)C + b0 + l : 0u;
-    const uint32_t ib = okb ? (uint32_t)(q0 + c) * (uint32_t)C + b0 + l : 0u;
-    const uint32_t ig = okg ? (uint32_t)(q0 + c) * (uint32_t)C + r0 + l : 0u;
-    A[l][c] = cmask<double>(gload<double>(gat<double>(Gg, ia)), oka);
-    B[l][c] = cmask<double>(gload<double>(gat<double>(Gg, ib)), okb);
-    Gt[l][c] = cmask<double>(gload<double>(gat<double>(Gg, ig)), okg);
+  if (mode == 0) {
+    ti = kb;
+    tj = kb + (int)blockIdx.x;
+    if (tj >= nt) return;
+  } else {
+    const int nrem = nt - kb - 1;
+    if (nrem <= 0 || (int)blockIdx.x >= nrem * (nrem + 1) / 2) return;
+    tile_of(blockIdx.x, nrem, ti, tj);
+    ti += kb + 1;
+    tj += kb + 1;
   }
-  __syncthreads();
+  const int k_lo = 32 * l0, k_hi = min(32 * l1, C);
+  if (k_lo >= k_hi) return;
+  z64* __restrict__ G = (z64*)descs[g].gram;
+  const gptr<const z64> Gg = as_global((const z64*)G);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const int i0 = (wave >> 1) * 16, j0 = (wave & 1) * 16;
+  const int i0 = ti * 32 + (wave >> 1) * 16, j0 = tj * 32 + (wave & 1) * 16;
+  const int ci = i0 + col, cj = j0 + col;
+  const bool oki = ci < C, okj = cj < C;
+  // every matrix here has C <= 1024: 32-bit element offsets
+  const uint32_t offi = (uint32_t)(oki ? ci : 0) * (uint32_t)C;
+  const uint32_t offj = (uint32_t)(okj ? cj : 0) * (uint32_t)C;
   typedef Mfma<double>::v4 V4;
   V4 acc[2];
 #pragma unroll
@@ -360,21 +360,45 @@ __global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ 
     acc[0][v] = 0.0;
     acc[1][v] = 0.0;
   }
+  // rows k0 + 4u + grp of the lane's two columns; a row at or beyond k_hi reads row k_lo
+  // (unconditional loads, masked where used)
+  z64 xa[4], ya[4], xn[4], yn[4];
+  auto load = [&](int k0, z64(&a)[4], z64(&b)[4]) {
 #pragma unroll
-  for (int k0 = 0; k0 < 32; k0 += 4)
-    gram_mfma<double>(acc, A[k0 + grp][i0 + col], B[k0 + grp][j0 + col]);
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + grp;
+      const uint32_t kc = (uint32_t)(k < k_hi ? k : k_lo);
+      a[u] = gload<double>(gat<double>(Gg, offi + kc));
+      b[u] = gload<double>(gat<double>(Gg, offj + kc));
+    }
+  };
+  load(k_lo, xa, ya);
+  for (int k0 = k_lo; k0 < k_hi; k0 += 16) {
+    load(k0 + 16 < k_hi ? k0 + 16 : k0, xn, yn);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool kok = k0 + 4 * u + grp < k_hi;
+      gram_mfma<double>(acc, cmask<double>(xa[u], oki && kok), cmask<double>(ya[u], okj && kok));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xa[u] = xn[u];
+      ya[u] = yn[u];
+    }
+  }
+  const gptr<z64> Gw = as_global(G);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    z64& z = Gt[i0 + Mfma<double>::row(lane, v)][j0 + col];
-    z.re -= acc[0][v];
-    z.im -= acc[1][v];
-  }
-  __syncthreads();
-  const gptr<z64> Gw = as_global(G);
-  for (int e = tid; e < 1024; e += 256) {
-    const int i = e & 31, j = e >> 5;
-    if (i < ni && j < nj && r0 + i <= q0 + j)
-      gstore<double>(gat<double>(Gw, (uint32_t)(q0 + j) * (uint32_t)C + r0 + i), Gt[i][j]);
+    const int i = i0 + Mfma<double>::row(lane, v);
+    if (i < C && okj && i <= cj) {
+      const gptr<z64> p = gat<double>(Gw, (uint32_t)cj * (uint32_t)C + (uint32_t)i);
+      z64 z = gload<double>(p);
+      z.re -= acc[0][v];
+      z.im -= acc[1][v];
+      gstore<double>(p, z);
+    }
   }
 }
 
@@ -498,16 +522,26 @@ void launch_gram64(const GateDesc* d_desc, int n_gates, int max_c, const Precond
                      d_desc, po);
 }
 
+// Panels of 32 columns; the trailing matrix is updated once per group of kGroup panels (a
+// rank-128 update), and each panel's block row, just before it is factored, by the rows of
+// the group's earlier panels.  Against a trailing update after every panel this reads and
+// writes the trailing tiles a quarter as often, with K loops four times as long.
 void launch_cholesky(const GateDesc* d_desc, int n_gates, int max_c, const PrecondOut& po,
                      hipStream_t stream) {
+  constexpr int kGroup = 4;
   const int nt = (max_c + 31) / 32;
   for (int kb = 0; kb < nt; ++kb) {
+    const int kb0 = kb - kb % kGroup;
+    if (kb > kb0)
+      hipLaunchKernelGGL(herk_kernel, dim3(nt - kb, n_gates), dim3(256), 0, stream, d_desc, kb,
+                         kb0, kb, 0);
     hipLaunchKernelGGL(potrf_kernel, dim3(n_gates), dim3(256), 0, stream, d_desc, po, kb);
     const int nrem = nt - kb - 1;
     if (nrem <= 0) break;
     hipLaunchKernelGGL(trsm_kernel, dim3(nrem, n_gates), dim3(256), 0, stream, d_desc, kb);
-    hipLaunchKernelGGL(herk_kernel, dim3(nrem * (nrem + 1) / 2, n_gates), dim3(256), 0, stream,
-                       d_desc, kb);
+    if (kb % kGroup == kGroup - 1)
+      hipLaunchKernelGGL(herk_kernel, dim3(nrem * (nrem + 1) / 2, n_gates), dim3(256), 0, stream,
+                         d_desc, kb, kb0, kb + 1, 1);
   }
 }
 
