@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void colsort_kernel(const GateDesc* __restrict
 
 // ---------------------------------------------------------------- Gram matrix
 // G[i, j] = sum_r conj(W[r, ps[i]]) W[r, ps[j]] in FP64 for the upper 32x32 tiles
-// (ti <= tj); column-major C x C.  Four waves, each a 16x16 sub-tile; rows in steps of 4.
+// (ti <= tj); column-major C x C.  Four waves, each a 16x16 sub-tile; rows in steps of 16.
 __device__ inline void tile_of(int t, int nt, int& ti, int& tj) {
   // upper-triangular tile t (row-major over ti, tj >= ti)
   ti = 0;
@@ -120,41 +120,51 @@ __global__ __launch_bounds__(256) void gram64_kernel(const GateDesc* __restrict_
   const uint32_t offi = (uint32_t)(oki ? ps[ci] : 0) * (uint32_t)R;
   const uint32_t offj = (uint32_t)(okj ? ps[cj] : 0) * (uint32_t)R;
   typedef Mfma<double>::v4 V4;
-  V4 acc[2];
-  for (int v = 0; v < 4; ++v) {
-    acc[0][v] = 0.0;
-    acc[1][v] = 0.0;
-  }
+  // three real products per entry: for conj(x) y with x = p + iq, y = u + iv,
+  // P1 = sum p u, P2 = sum q v, P3 = sum (p - q)(u + v); Re = P1 + P2, Im = P3 - P1 + P2.
+  // The inputs are FP32 values, so p - q, u + v and every product are exact in FP64.
+  V4 acc[3];
+  for (int j = 0; j < 3; ++j)
+    for (int v = 0; v < 4; ++v) acc[j][v] = 0.0;
   // 16 rows per step: the eight loads of a lane are unconditional (an out-of-range row
-  // reads row 0) and issued together, masked where used
-  for (int r0 = 0; r0 < R; r0 += 16) {
-    z32 xa[4], ya[4];
+  // reads row 0) and issued together, masked where used; the next step's are in flight
+  // during this step's products
+  z32 xa[4], ya[4], xn[4], yn[4];
+  auto load = [&](int r0, z32(&a)[4], z32(&b)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = r0 + 4 * u + grp;
       const uint32_t rc = r < R ? r : 0;
-      xa[u] = gload<float>(gat<float>(W, offi + rc));
-      ya[u] = gload<float>(gat<float>(W, offj + rc));
+      a[u] = gload<float>(gat<float>(W, offi + rc));
+      b[u] = gload<float>(gat<float>(W, offj + rc));
     }
+  };
+  load(0, xa, ya);
+  for (int r0 = 0; r0 < R; r0 += 16) {
+    load(r0 + 16 < R ? r0 + 16 : r0, xn, yn);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const bool rok = r0 + 4 * u + grp < R;
       const z32 a = cmask<float>(xa[u], oki && rok), b = cmask<float>(ya[u], okj && rok);
-      z64 x, y;
-      x.re = a.re;
-      x.im = a.im;
-      y.re = b.re;
-      y.im = b.im;
-      gram_mfma<double>(acc, x, y);
+      const double p = a.re, q = a.im, uu = b.re, vv = b.im;
+      acc[0] = Mfma<double>::op(p, uu, acc[0]);
+      acc[1] = Mfma<double>::op(q, vv, acc[1]);
+      acc[2] = Mfma<double>::op(p - q, uu + vv, acc[2]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xa[u] = xn[u];
+      ya[u] = yn[u];
     }
   }
   for (int v = 0; v < 4; ++v) {
     const int i = i0 + Mfma<double>::row(lane, v), j = j0 + col;
     if (i < C && j < C) {
       z64 z;
-      z.re = acc[0][v];
-      z.im = acc[1][v];
+      z.re = acc[0][v] + acc[1][v];
+      z.im = acc[2][v] - acc[0][v] + acc[1][v];
       G[(size_t)j * C + i] = z;
     }
   }
@@ -402,24 +412,49 @@ __global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ 
   }
 }
 
-// X = R^H in FP32 (C x C column-major, lower triangular) into the Jacobi work matrix.
-__global__ void xinit_kernel(const GateDesc* __restrict__ jdescs) {
+// X = R^H in FP32 (C x C column-major, lower triangular) into the Jacobi work matrix,
+// X[i, j] = conj(R[j, i]) = conj(G[j, i]) for i >= j.  One 32 x 32 tile of X per step,
+// transposed through LDS: G's column i is read along its rows j and X's column j written
+// along its rows i, both contiguous; tiles wholly above the diagonal are zeros.
+__global__ __launch_bounds__(256) void xinit_kernel(const GateDesc* __restrict__ jdescs) {
   const int g = blockIdx.y;
   const int C = jdescs[g].C;
+  const int nt = (C + 31) >> 5;
   const z64* __restrict__ G = (const z64*)jdescs[g].gram;
   z32* __restrict__ X = (z32*)jdescs[g].w;
-  const size_t total = (size_t)C * C;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % C), j = (int)(e / C);
-    z32 z;
-    z.re = z.im = 0.f;
-    if (i >= j) {
-      const z64 r = G[(size_t)i * C + j];  // R[j][i]
-      z.re = (float)r.re;
-      z.im = (float)(-r.im);
+  __shared__ z32 tile[32][33];  // tile[ii][jj] = X[32 a + ii, 32 b + jj]
+  const int tid = threadIdx.x;
+  for (int t = blockIdx.x; t < nt * nt; t += gridDim.x) {
+    const int a = t % nt, b = t / nt;  // tile row (X rows i) and column (X columns j)
+    if (a >= b) {
+      for (int e = tid; e < 1024; e += 256) {
+        const int jj = e & 31, ii = e >> 5;
+        const int i = 32 * a + ii, j = 32 * b + jj;
+        z32 z;
+        z.re = z.im = 0.f;
+        if (i < C && j < C && i >= j) {
+          const z64 r = G[(size_t)i * C + j];  // R[j][i]
+          z.re = (float)r.re;
+          z.im = (float)(-r.im);
+        }
+        tile[ii][jj] = z;
+      }
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        const int i = 32 * a + ii, j = 32 * b + jj;
+        if (i < C && j < C) X[(size_t)j * C + i] = tile[ii][jj];
+      }
+      __syncthreads();
+    } else {
+      for (int e = tid; e < 1024; e += 256) {
+        const int ii = e & 31, jj = e >> 5;
+        const int i = 32 * a + ii, j = 32 * b + jj;
+        z32 z;
+        z.re = z.im = 0.f;
+        if (i < C && j < C) X[(size_t)j * C + i] = z;
+      }
     }
-    X[e] = z;
   }
 }
 
@@ -449,8 +484,10 @@ __global__ void yhat_kernel(const GateDesc* __restrict__ jdescs, PrecondOut po, 
 }
 
 // U S = W Yhat for the kept columns (c = perm[j], j < k): 32 rows x 32 kept columns per
-// workgroup, four waves of 16 x 16, K = C in steps of 4 on FP32 MFMA.  Written into the
-// column c of the U buffer (R x C), unnormalized (the write-back divides by sigma).
+// workgroup, four waves of 16 x 16, K = C in steps of 16 on FP32 MFMA, the next step's loads
+// in flight.  Three real products per complex one: with a = x + iy, b = u + iv,
+// P1 = x u, P2 = y v, P3 = (x + y)(u + v); Re ab = P1 - P2, Im ab = P3 - P1 - P2.  Written
+// into the column c of the U buffer (R x C), unnormalized (the write-back divides by sigma).
 __global__ __launch_bounds__(256) void ugemm_kernel(const GateDesc* __restrict__ descs,
                                                     LayerOut out) {
   const int g = blockIdx.y;
@@ -471,29 +508,40 @@ __global__ __launch_bounds__(256) void ugemm_kernel(const GateDesc* __restrict__
   const int jl = jb + col;                              // B operand column of this lane
   const int cl = jl < k ? perm[jl] : -1;
   typedef Mfma<float>::v4 V4;
-  V4 acc[2];
-  for (int v = 0; v < 4; ++v) {
-    acc[0][v] = 0.f;
-    acc[1][v] = 0.f;
-  }
+  V4 acc[3];
+  for (int j = 0; j < 3; ++j)
+    for (int v = 0; v < 4; ++v) acc[j][v] = 0.f;
   // 16 values of K per step, the eight loads of a lane issued together (out-of-range
-  // indices read entry 0 and are masked)
+  // indices read entry 0 and are masked where used)
   const gptr<const z32> Wg = as_global(W), Yg = as_global(Y);
   const uint32_t rc = rr < R ? rr : 0, yoff = (uint32_t)(cl >= 0 ? cl : 0) * (uint32_t)C;
-  for (int k0 = 0; k0 < C; k0 += 16) {
-    z32 aa[4], bb[4];
+  z32 aa[4], bb[4], an[4], bn[4];
+  auto load = [&](int k0, z32(&a)[4], z32(&b)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int kk = k0 + 4 * u + grp;
       const uint32_t kc = kk < C ? kk : 0;
-      aa[u] = gload<float>(gat<float>(Wg, kc * (uint32_t)R + rc));
-      bb[u] = gload<float>(gat<float>(Yg, yoff + kc));
+      a[u] = gload<float>(gat<float>(Wg, kc * (uint32_t)R + rc));
+      b[u] = gload<float>(gat<float>(Yg, yoff + kc));
     }
+  };
+  load(0, aa, bb);
+  for (int k0 = 0; k0 < C; k0 += 16) {
+    load(k0 + 16 < C ? k0 + 16 : k0, an, bn);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const bool kok = k0 + 4 * u + grp < C;
-      cmfma<float>(acc, cmask<float>(aa[u], rr < R && kok), cmask<float>(bb[u], cl >= 0 && kok));
+      const z32 a = cmask<float>(aa[u], rr < R && kok), b = cmask<float>(bb[u], cl >= 0 && kok);
+      acc[0] = Mfma<float>::op(a.re, b.re, acc[0]);
+      acc[1] = Mfma<float>::op(a.im, b.im, acc[1]);
+      acc[2] = Mfma<float>::op(a.re + a.im, b.re + b.im, acc[2]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      aa[u] = an[u];
+      bb[u] = bn[u];
     }
   }
   for (int v = 0; v < 4; ++v) {
@@ -501,8 +549,8 @@ __global__ __launch_bounds__(256) void ugemm_kernel(const GateDesc* __restrict__
     const int j = jb + col;
     if (r < R && j < k) {
       z32 z;
-      z.re = acc[0][v];
-      z.im = acc[1][v];
+      z.re = acc[0][v] - acc[1][v];
+      z.im = acc[2][v] - acc[0][v] - acc[1][v];
       U[(size_t)perm[j] * R + r] = z;
     }
   }
@@ -546,7 +594,8 @@ void launch_cholesky(const GateDesc* d_desc, int n_gates, int max_c, const Preco
 }
 
 void launch_xinit(const GateDesc* d_jdesc, int n_gates, int max_c, hipStream_t stream) {
-  const int blocks = std::max(1, std::min(256, (max_c * max_c + 255) / 256));
+  const int nt = (max_c + 31) / 32;
+  const int blocks = std::max(1, std::min(256, nt * nt));
   hipLaunchKernelGGL(xinit_kernel, dim3(blocks, n_gates), dim3(256), 0, stream, d_jdesc);
 }
 
