@@ -250,7 +250,8 @@ def test_random_circuits_match_oracle(precision, family, reading):
         n, layers = 21, circuits.rqc_1d(21, 20, seed=3)
     else:
         n, layers = 16, circuits.rqc_2d(4, 4, 8, seed=3)
-    tol = 1e-10 if precision == "fp64" else 2e-5
+    # FP32: Lambda 1.9e-6, norm 1.5e-6 relative, fidelity error 2.5e-11 at most (measured)
+    tol = 1e-10 if precision == "fp64" else 5e-6
 
     def check(li, m, ref, st):
         say(f"{family} {precision} {reading} layer {li + 1}/{len(layers)}")
@@ -259,7 +260,7 @@ def test_random_circuits_match_oracle(precision, family, reading):
 
     m, ref = _run_pair(n, layers, 8, precision, reading, check=check)
     err = po.fidelity_error(ref, to_oracle(m))
-    assert err <= (1e-12 if precision == "fp64" else 1e-8)
+    assert err <= (1e-12 if precision == "fp64" else 1e-9)
     assert abs(m.norm() - po.norm(ref)) <= tol * po.norm(ref)
     m.close()
 
@@ -274,8 +275,8 @@ def test_pqc_1d_exact_regime_matches_statevector(precision):
     m, ref = _run_pair(n, layers, 128, precision, "literal")
     psi = sv.run_circuit(n, layers)
     dense = po.to_dense(to_oracle(m))
-    assert 1.0 - sv.fidelity(psi, dense) <= (1e-12 if precision == "fp64" else 1e-9)
-    assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 1e-5)
+    assert 1.0 - sv.fidelity(psi, dense) <= (1e-12 if precision == "fp64" else 1e-10)
+    assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 3e-6)
     m.close()
 
 
@@ -287,7 +288,7 @@ def test_pqc_2d_truncation_values_match_oracle(precision):
     the first truncating one, where the kept values, k and eps are unique."""
     from paper_2312_02667_amd import circuits
     n, layers = 16, circuits.pqc_2d(4, 4, 8, seed=3)
-    tol = 1e-10 if precision == "fp64" else 2e-5
+    tol = 1e-10 if precision == "fp64" else 1e-6  # FP32: 1.3e-7 measured
     seen = {"trig": False}
 
     def check(li, m, ref, st):
@@ -310,8 +311,9 @@ def test_norm_stabilization_ablation_on_gpu(precision):
     n, depth, chi = 21, 160, 4
     layers = circuits.rqc_1d(n, depth, seed=8)
     # 1600 truncating updates at chi = 4 amplify FP32 rounding along the trajectory: the
-    # norms drift apart by ~1e-3 relative after 150 layers (measured); FP64 stays at 1e-12
-    rtol = 1e-9 if precision == "fp64" else 1e-2
+    # norms drift apart by up to 3.4e-4 relative by layer 160 (measured: 1.5e-6 at layer 50,
+    # 8.7e-6 at layer 100); FP64 stays at 1e-12
+    rtol = 1e-9 if precision == "fp64" else 1e-3
     for stabilize in (False, True):
         norms = []
 

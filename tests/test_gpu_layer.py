@@ -31,17 +31,18 @@ def test_small_exact_circuit(precision, seed):
         assert lambda_diff(to_oracle(m), ref) <= lam_tol
         # nothing is compressed, so no nu is applied (Algorithm 1's "else" branch)
         assert np.all(st["nu"] == 1.0)
-    f_tol = 1e-12 if precision == "fp64" else 1e-9
+    f_tol = 1e-12 if precision == "fp64" else 1e-10
     dense = po.to_dense(to_oracle(m))
     assert 1 - sv.fidelity(psi, dense) <= f_tol
-    # FP32 Jacobi rotations keep column norms to ~u sqrt(rotations per column) per update
-    # (~1e-6 per bond at these sizes), so the norm and <Z> carry ~1e-5 after 36 gates
-    assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 1e-5)
-    assert np.max(np.abs(m.expect_z() - sv.expect_z(psi, n))) <= (1e-12 if precision == "fp64" else 1e-5)
+    # FP32 Jacobi rotations keep column norms to ~u sqrt(rotations per column) per update,
+    # so the norm and <Z> carry a few 1e-7 after 36 gates (3.6e-7 and 3.9e-7 measured)
+    assert abs(m.norm() - 1.0) <= (1e-12 if precision == "fp64" else 2e-6)
+    assert np.max(np.abs(m.expect_z() - sv.expect_z(psi, n))) <= (1e-12 if precision == "fp64" else 2e-6)
     # FP32 recovers the left vectors as theta Y / sigma (preconditioned SVD): their
     # orthogonality error is ~u sigma_1 / sigma_j for the smallest kept sigma_j (absolute,
-    # LAPACK-like accuracy), which the canonical distance sees directly: 3.7e-5 measured
-    assert m.canon_distance() <= (1e-10 if precision == "fp64" else 2e-4)
+    # LAPACK-like accuracy), which the canonical distance sees directly: 6.9e-6 measured
+    # with the Jacobi converged to u sqrt(R)
+    assert m.canon_distance() <= (1e-10 if precision == "fp64" else 2e-5)
     m.close()
 
 
@@ -101,14 +102,17 @@ def test_ptsu_and_no_stabilize_match_oracle(precision):
             assert m.bond_dims() == ref.bond_dims()
             # complement reading: nu rescales Lambda by the FP32 kept weight at every update
             # (~u sqrt(chi) relative each), so Lambda drifts like the norm bound below
-            lam_tol = 1e-10 if precision == "fp64" else (5e-5 if rel == "complement" else 1e-5)
+            # (measured: 1.6e-5 complement, at most 1.1e-6 otherwise)
+            lam_tol = 1e-10 if precision == "fp64" else (3e-5 if rel == "complement" else 3e-6)
             assert lambda_diff(to_oracle(m), ref) <= lam_tol
         # under the complement reading nu_i rescales by the kept weight of the FP32 theta,
         # whose squared norm carries ~u sqrt(chi) relative rounding: a few 1e-7 per update,
-        # ~1e-5 over the ~90 updates (gates and tSU) of this circuit
-        norm_tol = 1e-10 if precision == "fp64" else (5e-5 if rel == "complement" else 1e-5)
+        # ~1e-5 over the ~90 updates (gates and tSU) of this circuit (2.4e-5 measured; at
+        # most 1.1e-6 on the other readings)
+        norm_tol = 1e-10 if precision == "fp64" else (5e-5 if rel == "complement" else 3e-6)
         assert abs(m.norm() - po.norm(ref)) <= norm_tol
-        assert abs(m.canon_distance() - po.canon_distance(ref)) <= (1e-9 if precision == "fp64" else 1e-4)
+        # 9.2e-6 measured under the complement reading, at most 4.1e-7 otherwise
+        assert abs(m.canon_distance() - po.canon_distance(ref)) <= (1e-9 if precision == "fp64" else 2e-5)
         m.close()
 
 
@@ -144,7 +148,8 @@ def test_queries_match_oracle(precision):
     mb = ptebd.MPS(n, 16, "fp64")
     ma.import_state(ga, la)
     mb.import_state(gb, lb)
-    tol = 1e-12 if precision == "fp64" else 1e-5
+    # an imported state: FP32 storage rounding only (norm 8.9e-9 relative measured)
+    tol = 1e-12 if precision == "fp64" else 1e-6
     say(f"queries {precision}")
     assert abs(ma.norm() - po.norm(a)) <= tol * po.norm(a)
     ov = ma.overlap(mb)
