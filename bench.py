@@ -187,9 +187,10 @@ def roofline(kstats, precision, updates, chi, n_steps, step_ms):
     alg = svd_reference_flops(chi) * updates
     achieved = alg / jac_s / 1e12
     executed = jac["flops"] / jac_s / 1e12
+    traffic = measured_traffic("jacobi_round", precision)
     out = {"bound": "mfma", "kernel": "jacobi_round", "achieved": achieved, "peak": peak,
            "unit": "TFLOP/s", "frac": achieved / peak,
-           "traffic": measured_traffic("jacobi_round", precision),
+           "traffic": traffic,
            "count": "88 (2 chi)^3 flops per bond update (SVD reference count), over the "
                     "Jacobi rounds' event time",
            "launches": jac["launches"], "avg_launch_ms": jac["total_ms"] / launches,
@@ -197,6 +198,11 @@ def roofline(kstats, precision, updates, chi, n_steps, step_ms):
            "executed_frac": executed / peak,
            # three real MFMA products per complex multiply-add (8 algorithmic flops as 6)
            "mfma_issued_frac": 0.75 * executed / peak}
+    if traffic is not None:
+        # HBM bytes per launch (rocprofv3 counters) over this run's average launch time
+        hbm = traffic / (jac["total_ms"] / launches / 1e3) / 1e12
+        out["hbm_tbps"] = hbm
+        out["hbm_frac"] = hbm / (HBM_GBS / 1e3)
     th = kstats["theta"]
     th_alg = theta_flops(chi) * updates
     th_frac = th_alg / (th["total_ms"] / 1e3) / 1e12 / peak if th["total_ms"] > 0 else None

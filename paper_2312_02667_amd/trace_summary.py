@@ -6,6 +6,9 @@ layers after the set-up ones, found by counting theta dispatches: each layer of 
 as two halves, two theta dispatches) with the union of each kernel class's dispatch intervals
 set against the event timing that ``bench.py`` printed for the same run.
 
+``counters``: rocprofv3's MFMA utilisation (MFMA busy cycles over active cycles) and the
+instruction mix of the timed Jacobi and theta dispatches from one ``--pmc`` pass.
+
 ``traffic``: HBM bytes per Jacobi launch from two ``--pmc`` runs (FETCH_SIZE, WRITE_SIZE, KiB
 per dispatch), each scaled by what the same counter read for ``hbm_copy_kernel`` (bench's
 ``--copy-calibration MIB``: MIB MiB read and MIB MiB written per dispatch).  A launch is what
@@ -247,6 +250,57 @@ def cmd_traffic(a) -> None:
           f"({t_hbm / t_alg:.2f}x its {t_alg:.4e} algorithmic bytes) |")
 
 
+COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+            "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE", "SQ_INSTS_VALU", "SQ_INSTS_MFMA",
+            "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE")
+
+
+def cmd_counters(a) -> None:
+    """MFMA utilisation and instruction mix of the timed Jacobi and theta dispatches from one
+    --pmc pass (the profiler serializes dispatches while it counts, so each dispatch ran
+    alone).  GRBM_GUI_ACTIVE is summed over the XCDs, so one XCD's active cycles are its sum
+    over xcds; MFMA utilisation is the busy cycles summed over the SIMDs over (active cycles x
+    SIMDs), rocprofv3's MfmaUtil."""
+    per = defaultdict(dict)
+    names = {}
+    for r in csv.DictReader(open(a.csv)):
+        d = int(r["Dispatch_Id"])
+        per[d][r["Counter_Name"]] = float(r["Counter_Value"])
+        names[d] = (short_name(r["Kernel_Name"]), int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+    theta_ids = sorted(d for d, n in names.items() if n[0] == f"theta_kernel<{CTYPE[a.precision]}>")
+    t0 = theta_ids[2 * a.setup_layers]
+    mops = "SQ_INSTS_VALU_MFMA_MOPS_F32" if a.precision == "fp32" else "SQ_INSTS_VALU_MFMA_MOPS_F64"
+    print("| kernel (timed dispatches) | dispatches | MFMA flops issued | MFMA busy (MfmaUtil) | "
+          "issued MFMA rate | VALU per MFMA | LDS per MFMA | LDS bank conflict cycles / active |")
+    print("|---|---|---|---|---|---|---|---|")
+    peak = 157.3e12 if a.precision == "fp32" else 78.6e12
+    for label, pick in (("jacobi_round", lambda n: is_jacobi(n, a.precision)),
+                        ("theta", lambda n: n == f"theta_kernel<{CTYPE[a.precision]}>")):
+        ids = [d for d in per if d >= t0 and pick(names[d][0])]
+        if not ids:
+            continue
+        tot = defaultdict(float)
+        ns = 0
+        for d in ids:
+            for c, v in per[d].items():
+                tot[c] += v
+            ns += names[d][2] - names[d][1]
+        flops = 512.0 * tot[mops]
+        active = tot["GRBM_GUI_ACTIVE"] / a.xcds
+        util = tot["SQ_VALU_MFMA_BUSY_CYCLES"] / (active * a.simds) if active else float("nan")
+        rate = flops / (ns * 1e-9) if ns else float("nan")
+        mf = tot["SQ_INSTS_MFMA"] or float("nan")
+        lds_act = tot["SQ_LDS_IDX_ACTIVE"]
+        conf = tot["SQ_LDS_BANK_CONFLICT"] / lds_act if lds_act else float("nan")
+        print(f"| {label} | {len(ids)} | {flops:.4e} | {util:.3f} | {rate / 1e12:.1f} TFLOP/s "
+              f"({rate / peak:.3f} of peak) | {tot['SQ_INSTS_VALU'] / mf:.1f} | "
+              f"{tot['SQ_INSTS_LDS'] / mf:.2f} | {conf:.3f} |")
+    print()
+    print(f"Dispatch durations from the counter pass's own timestamps; active cycles per XCD "
+          f"over the summed durations give a clock of "
+          f"{sum(per[d].get('GRBM_GUI_ACTIVE', 0) for d in per if d >= t0) / a.xcds / max(1, sum(names[d][2] - names[d][1] for d in per if d >= t0)):.2f} GHz.")
+
+
 def main(argv=None) -> None:
     p = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = p.add_subparsers(dest="cmd", required=True)
@@ -265,8 +319,14 @@ def main(argv=None) -> None:
     w.add_argument("--precision", default="fp32", choices=list(CTYPE))
     w.add_argument("--setup-layers", type=int, default=9)
     w.add_argument("--copy-mib", type=int, default=256)
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--precision", default="fp32", choices=list(CTYPE))
+    c.add_argument("--setup-layers", type=int, default=9)
+    c.add_argument("--xcds", type=int, default=8)
+    c.add_argument("--simds", type=int, default=1024)
     a = p.parse_args(argv)
-    cmd_trace(a) if a.cmd == "trace" else cmd_traffic(a)
+    {"trace": cmd_trace, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
