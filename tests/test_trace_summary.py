@@ -1,5 +1,6 @@
 """The rocprofv3 summariser on small synthetic CSVs: interval unions, the timed window found by
-counting theta dispatches, and the copy-calibrated HBM bytes per counted Jacobi launch."""
+counting theta dispatches, the copy-calibrated HBM bytes per counted Jacobi launch, and the
+MFMA utilisation and instruction mix from SQ counters."""
 
 import csv
 import json
@@ -91,3 +92,29 @@ def test_traffic_scaled_by_the_copy(tmp_path, capsys):
     assert f"hbm_bytes_per_launch: {(400 + 100) * 1024.0:.6e}" in out
     assert "scale factor 2.0000" in out and "scale factor 1.0000" in out
     assert len(ts.kernel_source_digest()) == 64
+
+
+def test_counters_mfma_utilisation(tmp_path, capsys):
+    rows = []
+    # one set-up layer (two theta dispatches), then the timed layer: two theta dispatches and
+    # two Jacobi dispatches of 1 ms each
+    plan = [(THETA, 0, 1), (THETA, 1, 2), (THETA, 10, 11), (THETA, 11, 12),
+            (JAC, 1_000_000, 2_000_000), (JAC, 2_000_000, 3_000_000)]
+    for i, (name, a, b) in enumerate(plan):
+        vals = {"SQ_INSTS_VALU_MFMA_MOPS_F32": 1000.0, "SQ_VALU_MFMA_BUSY_CYCLES": 1024 * 600.0,
+                "GRBM_GUI_ACTIVE": 8 * 2400.0, "SQ_INSTS_VALU": 120.0, "SQ_INSTS_MFMA": 10.0,
+                "SQ_INSTS_LDS": 20.0, "SQ_LDS_BANK_CONFLICT": 5.0, "SQ_LDS_IDX_ACTIVE": 50.0}
+        for c, v in vals.items():
+            rows.append({k: 0 for k in PMC_COLS} | {"Dispatch_Id": i + 1, "Kernel_Name": name,
+                                                     "Counter_Name": c, "Counter_Value": v,
+                                                     "Start_Timestamp": a, "End_Timestamp": b})
+    p = tmp_path / "c.csv"
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=PMC_COLS)
+        w.writeheader()
+        w.writerows(rows)
+    ts.main(["counters", "--csv", str(p), "--setup-layers", "1"])
+    out = capsys.readouterr().out
+    # busy 600 of 2400 active cycles per SIMD; 2 x 1000 x 512 flops in 2 ms
+    assert "| jacobi_round | 2 | 1.0240e+06 | 0.250 |" in out
+    assert "| 12.0 | 2.00 | 0.100 |" in out
