@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libptebd.so")
 COPY_LIB = os.path.join(HERE, "libhbmcopy.so")
 COPY_SOURCE = "hbm_copy.hip"
 SOURCES = ["ptebd_api.hip", "ptebd_kernels.hip", "ptebd_queries.hip", "ptebd_sample.hip",
-           "ptebd_precond.hip", "ptebd_noalloc.hip", "ptebd_jacobi64.hip"]
+           "ptebd_precond.hip", "ptebd_noalloc.hip", "ptebd_jacobi64.hip", "ptebd_theta.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [
