@@ -61,9 +61,9 @@ __global__ void jacobi_init_kernel(const GateDesc* __restrict__ descs, LayerOut 
 // sums): a quarter fewer MFMAs, for an error bound of the same order (normwise, a few units
 // of the roundoff of T times the norms of the two factors).
 //
-// LDS: G and Q (2 x 32 x 33 complex T), both rotated in place, and Re + Im of the permuted
-// Q; the cross-wave reduction of the Gram tiles and the permuted copy of Q used by the
-// column update alias G and Q.
+// LDS: G and Q (2 x 32 rows of 48 (FP32) or 33 (FP64) complex T), both rotated in place, and
+// Re + Im of the permuted Q; the cross-wave reduction of the Gram tiles and the permuted copy
+// of Q used by the column update alias G and Q.
 //
 // Occupancy: the kernel is bound by the latency of its phases, so it is built for at least
 // five waves per SIMD in FP32 (at most 96 registers, no spills) and three in FP64 (at most
@@ -106,10 +106,14 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   const gptr<cplx<T>> __restrict__ W = as_global((cplx<T>*)d->w);
   const gptr<cplx<T>> __restrict__ V = as_global((cplx<T>*)d->v);
 
-  __shared__ cplx<T> G[32][33];
-  __shared__ cplx<T> Q[32][33];
+  // FP32 rows padded to 48 entries (384 B): the two 16-lane row groups of each half-wave of
+  // an 8-byte LDS access then fall on disjoint banks (a 33-entry row puts them 8 B apart).
+  // FP64 entries are 16 B, whose accesses are conflict-free at 33.
+  constexpr int kLd = sizeof(T) == 4 ? 48 : 33;
+  __shared__ cplx<T> G[32][kLd];
+  __shared__ cplx<T> Q[32][kLd];
   __shared__ __align__(16) T P[16][4];  // one round's rotations: c, Re s, Im s, (unused)
-  __shared__ T Qs[32][33];  // Re + Im of the permuted Q
+  __shared__ T Qs[32][kLd];  // Re + Im of the permuted Q
   __shared__ double red[4];
   __shared__ unsigned int rmax_bits;  // largest |g|^2 / (a b) rotated in this inner sweep
   __shared__ int pos[32];
@@ -459,7 +463,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 5 : 3) void jacobi_round_kern
   __syncthreads();
   // column-permuted copy of Q in G, which is no longer needed, and Re + Im of its entries
   // for the three-product complex multiply of the update
-  cplx<T>(*Qp)[33] = G;
+  cplx<T>(*Qp)[kLd] = G;
   for (int e = tid; e < 1024; e += 256) {
     const int i = e >> 5, j = e & 31;
     const cplx<T> z = Q[i][j];
