@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ptebd.h"
@@ -352,7 +353,7 @@ OutLayout out_layout(int n, int cmax) {
 
 LayerOut make_layer_out(void* base, const OutLayout& L, int cmax) {
   char* b = (char*)base;
-  LayerOut o;
+  LayerOut o{};
   o.sig = (double*)(b + L.sig);
   o.perm = (int32_t*)(b + L.perm);
   o.k = (int32_t*)(b + L.k);
@@ -430,7 +431,20 @@ struct SweepArgs {
 
 template <class X>
 void append_key(std::string& k, const X& x) {
+  static_assert(std::is_arithmetic<X>::value || std::is_pointer<X>::value,
+                "keys are built from scalar fields (a struct's padding bytes are indeterminate)");
   k.append(reinterpret_cast<const char*>(&x), sizeof(X));
+}
+
+// The fields of a LayerOut a sweep's launches read, one by one.
+void append_key(std::string& k, const LayerOut& o) {
+  for (const void* p : {(const void*)o.sig, (const void*)o.perm, (const void*)o.k,
+                        (const void*)o.r, (const void*)o.eps, (const void*)o.nu,
+                        (const void*)o.sweeps, (const void*)o.conv, (const void*)o.offbits,
+                        (const void*)o.counters, (const void*)o.work, (const void*)o.rstart})
+    append_key(k, p);
+  for (int32_t v : {o.nslot, o.nbmax, o.triangular, o.block_cols, o.cmax})
+    append_key(k, v);
 }
 
 // Sweep s of a pipeline on `stream`: its nbp - 1 rounds and the convergence check that counts
