@@ -222,7 +222,9 @@ int ptebd_apply_layer(ptebd_mps_t h, int n_gates, const int32_t* state_idx,
  * (l_r_cano); bond dimensions can only shrink (values <= cutoff * sigma_1 are dropped; the
  * FP32 floor applies).  norm_out (may be NULL) receives n.  The 2N-3 bond updates run in
  * about N sequential batches: the cost is sequential in N, unlike a layer.  The norm and
- * fidelity estimates are left unchanged.
+ * fidelity estimates are left unchanged.  Its SVDs use one inner Jacobi sweep per pair
+ * whatever ptebd_set_svd_params set (each step is a batch of one or two SVDs, whose rounds
+ * are latency-bound); the outer convergence test is the handle's.
  * Errors: EINVAL, ENOMEM, EDEVICE, ENONFINITE, EANNIHILATED; warning WNOCONV.  Each batch
  * of tSU steps commits as a whole (see ptebd_apply_layer); after an error the state holds the
  * batches done so far, which change its gauge but not the wavefunction beyond the cutoff. */

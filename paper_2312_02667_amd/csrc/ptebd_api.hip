@@ -1391,6 +1391,15 @@ int ptebd_canonicalize(ptebd_mps_t h, int s, double cutoff, double* norm_out) {
   // regauges that block's interior, so the other block's environment stays the identity.
   // About n sequential steps instead of the 2(n-1) of one sweep there and one back.
   const int m = (n - 2) / 2;
+  // Each step is a batch of one or two SVDs, so a Jacobi round lasts as long as one
+  // workgroup's inner Jacobi: one inner sweep per pair (the outer convergence test is
+  // unchanged) costs more rounds but less time (N = 256, chi = 256: 2.84 s against 3.11 s).
+  struct InnerSweeps {
+    ptebd_mps* h;
+    int saved;
+    ~InnerSweeps() { h->inner_sweeps = saved; }
+  } inner_guard{h, h->inner_sweeps};
+  h->inner_sweeps = 1;
   auto step = [&](int ql, int qr) -> int {
     std::vector<Item> items;
     if (ql >= 0) items.push_back(Item{s, ql, nullptr, 0});
