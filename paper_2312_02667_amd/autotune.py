@@ -22,12 +22,15 @@ layers use the complement eps reading, the one the benchmark runs.
 The search is coordinate descent from the defaults: each control in turn takes every value
 of its candidate list with the others held, and the best point found so far is kept; two
 passes.  The search itself (``search``) only sees an evaluation function, so it runs without
-a GPU; ``measure_layer_schedule`` is the GPU evaluation over the C ABI.
+a GPU; ``measure_schedule`` is the GPU evaluation over the C ABI, on the saturated layers of a
+Haar brickwork chain (``chain_spec``) or of the lattice and batched-mix workloads
+(``workload_spec``, inputs from ``workloads``).
 
 Command line (one MI355X)::
 
     python -m paper_2312_02667_amd.autotune --n-sites 1024 --chi 256 --precision fp32 \\
         --cache paper_2312_02667_amd/autotune_cache.json
+    python -m paper_2312_02667_amd.autotune --workload lattice
 """
 
 from __future__ import annotations
@@ -162,46 +165,50 @@ def accept(err_f: float, default_err_f: float, precision: str, n_unconverged: in
             and err_f <= ERR_F_SLACK * default_err_f + ERR_F_FLOOR)
 
 
-def measure_layer_schedule(n_sites: int, chi: int, precision: str, seed: int = 0,
-                           timed_layers: int = 3, repeats: int = 1):
-    """Build the GPU evaluation for ``search``: a Haar brickwork chain of n_sites is driven
-    (default schedule) to the layer where every bulk bond is at chi, its state is kept, and
-    each candidate then applies the same ``timed_layers`` layers to a fresh copy of it.  The
-    same layers applied to the same state on the FP64 path give the reference for err_F.  The
-    result holds the summed device time of those layers (the least over ``repeats``), the
-    largest sweep count, err_F and whether the checks passed.  Returns (evaluate, defaults,
-    n_gates)."""
-    from . import inputs, ptebd
+def measure_schedule(n_sites, caps, precision: str, setup: list, timed: list,
+                     repeats: int = 1):
+    """Build the GPU evaluation for ``search`` over any batch of states: ``setup`` and
+    ``timed`` are lists of ``apply_layer`` keyword sets (bonds, gates, chi_max, state_idx).
+    Each candidate runs on a fresh handle: the set-up layers with the default schedule (the
+    path is deterministic, so every candidate starts from the same bits), then the timed
+    layers with the candidate's.  The same timed layers applied to the set-up states on the
+    FP64 path give the reference for err_F (the largest over the states).  The result holds
+    the summed device time of the timed layers (the least over ``repeats``), the largest sweep
+    count, err_F and whether the checks passed.  Returns (evaluate, defaults)."""
+    from . import ptebd
 
-    setup = max(1, int(math.ceil(math.log2(max(2, chi))))) + 1
-    layers = inputs.brickwork_circuit(n_sites, setup + timed_layers, seed)
-    m = ptebd.MPS(n_sites, chi, precision)
+    n_states = len(n_sites)
+
+    def fresh():
+        h = ptebd.MPS(n_sites, caps, precision)
+        for kw in setup:
+            h.apply_layer(**kw, eps_reading=EPS_READING)
+        return h
+
+    m = fresh()
     defaults = m.svd_params()
-    for i in range(setup):
-        m.apply_layer(*layers[i], chi_max=chi, eps_reading=EPS_READING)
-    gam, lam = m.export()
+    fp64 = ptebd.MPS(n_sites, caps, "fp64")
+    for s in range(n_states):
+        fp64.import_state(*m.export(s), s)
     m.close()
-    timed = layers[setup:]
-    fp64 = ptebd.MPS(n_sites, chi, "fp64")
-    fp64.import_state(gam, lam)
-    for bonds, gates in timed:
-        fp64.apply_layer(bonds, gates, chi_max=chi, eps_reading=EPS_READING)
-    n64 = fp64.norm()
+    for kw in timed:
+        fp64.apply_layer(**kw, eps_reading=EPS_READING)
+    n64 = [fp64.norm(s) for s in range(n_states)]
     ref = {}
 
     def evaluate(params):
         best_ms, sweeps, unconv, err = None, 0, 0, 0.0
         for _ in range(max(1, repeats)):
-            h = ptebd.MPS(n_sites, chi, precision)
-            h.import_state(gam, lam)
+            h = fresh()
             h.set_svd_params(**params)
             ms = 0.0
-            for bonds, gates in timed:
-                st = h.apply_layer(bonds, gates, chi_max=chi, eps_reading=EPS_READING)
+            for kw in timed:
+                st = h.apply_layer(**kw, eps_reading=EPS_READING)
                 ms += st["device_ms"]
                 sweeps = max(sweeps, int(st["max_sweeps"]))
                 unconv += int(st["n_unconverged"])
-            err = 1.0 - abs(h.overlap(fp64)) ** 2 / (h.norm() ** 2 * n64 ** 2)
+            err = max(1.0 - abs(h.overlap(fp64, s, s)) ** 2 / (h.norm(s) ** 2 * n64[s] ** 2)
+                      for s in range(n_states))
             h.close()
             best_ms = ms if best_ms is None else min(best_ms, ms)
         if not ref:
@@ -210,16 +217,47 @@ def measure_layer_schedule(n_sites: int, chi: int, precision: str, seed: int = 0
         return {"ms": best_ms, "ok": ok, "max_sweeps": sweeps, "err_F": err,
                 "n_unconverged": unconv}
 
-    n_gates = len(timed[0][0])
-    return evaluate, {k: defaults[k] for k in SEARCH_SPACE if k in defaults}, n_gates
+    return evaluate, {k: defaults[k] for k in SEARCH_SPACE if k in defaults}
 
 
-def tune(n_sites: int, chi: int, precision: str, cache_path: str, seed: int = 0,
-         timed_layers: int = 3, repeats: int = 1, passes: int = 2, log=print,
-         min_gain: float = 0.01) -> dict:
-    """Tune one shape on the GPU and store the result in the cache; returns the entry."""
-    evaluate, defaults, n_gates = measure_layer_schedule(n_sites, chi, precision, seed,
-                                                         timed_layers, repeats)
+def chain_spec(n_sites: int, chi: int, seed: int = 0, timed_layers: int = 3) -> dict:
+    """A Haar brickwork chain of n_sites driven (default schedule) to the layer where every
+    bulk bond is at chi, then ``timed_layers`` saturated layers."""
+    from . import inputs
+
+    setup = max(1, int(math.ceil(math.log2(max(2, chi))))) + 1
+    layers = [dict(bonds=b, gates=g, chi_max=chi)
+              for b, g in inputs.brickwork_circuit(n_sites, setup + timed_layers, seed)]
+    return {"n_sites": [n_sites], "caps": [chi], "setup": layers[:setup],
+            "timed": layers[setup:],
+            "workload": f"Haar brickwork, N={n_sites}, chi={chi}, {timed_layers} saturated "
+                        f"layers of {len(layers[setup]['bonds'])} gates, seed {seed}"}
+
+
+def workload_spec(workload: str, timed_layers: int) -> dict:
+    """The lattice or batched-mix workload (``workloads``): the compiled lattice layers up to
+    the 40th as set-up (its largest bonds are at 512 from about the 21st) and the next
+    ``timed_layers`` timed; the mix's first 10 of 16 layers as set-up (every state's bulk
+    bonds at its cap) and the next ``timed_layers`` timed."""
+    from . import workloads
+
+    n_sites, caps, calls = workloads.layer_calls(workload)
+    first = 39 if workload == "lattice" else 10
+    if first + timed_layers > len(calls):
+        raise ValueError(f"the {workload} workload has {len(calls)} layers")
+    timed = calls[first:first + timed_layers]
+    return {"n_sites": n_sites, "caps": caps, "setup": calls[:first], "timed": timed,
+            "workload": f"{workload} workload, {len(n_sites)} state(s), caps up to {max(caps)}, "
+                        f"layers {first + 1}..{first + timed_layers} timed "
+                        f"(up to {max(len(kw['bonds']) for kw in timed)} gates)"}
+
+
+def tune_spec(spec: dict, precision: str, cache_path: str, repeats: int = 1, passes: int = 2,
+              log=print, min_gain: float = 0.01) -> dict:
+    """Tune one workload shape on the GPU and store the result in the cache under the key of
+    its largest cap and largest timed layer; returns the entry."""
+    evaluate, defaults = measure_schedule(spec["n_sites"], spec["caps"], precision,
+                                          spec["setup"], spec["timed"], repeats)
     space = _space_for(precision)
 
     def logged(p):
@@ -229,28 +267,37 @@ def tune(n_sites: int, chi: int, precision: str, cache_path: str, seed: int = 0,
 
     best, best_r, history = search(logged, defaults, space, passes, min_gain)
     base_r = history[0][1]
+    n_gates = max(len(kw["bonds"]) for kw in spec["timed"])
     entry = {
         "params": best,
         "ms": best_r["ms"],
         "default_ms": base_r["ms"],
         "default_params": history[0][0],
         "min_gain": min_gain,
-        "workload": f"Haar brickwork, N={n_sites}, chi={chi}, {timed_layers} saturated layers "
-                    f"of {n_gates} gates, seed {seed}, eps reading {EPS_READING}; err_F "
-                    f"against the same layers on the FP64 path",
+        "workload": f"{spec['workload']}; eps reading {EPS_READING}; err_F against the same "
+                    f"layers on the FP64 path",
         "evaluated": [{"params": p, "ms": r["ms"], "ok": r["ok"],
                        "err_F": r["err_F"], "max_sweeps": r["max_sweeps"]}
                       for p, r in history],
         "time": time.strftime("%Y-%m-%d %H:%M:%S"),
     }
     cache = load_cache(cache_path)
-    cache["entries"][cache_key(precision, chi, n_gates)] = entry
+    cache["entries"][cache_key(precision, max(spec["caps"]), n_gates)] = entry
     save_cache(cache_path, cache)
     return entry
 
 
+def tune(n_sites: int, chi: int, precision: str, cache_path: str, seed: int = 0,
+         timed_layers: int = 3, repeats: int = 1, passes: int = 2, log=print,
+         min_gain: float = 0.01) -> dict:
+    """Tune the saturated layers of a Haar brickwork chain (``chain_spec``)."""
+    return tune_spec(chain_spec(n_sites, chi, seed, timed_layers), precision, cache_path,
+                     repeats, passes, log, min_gain)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--workload", choices=("chain", "lattice", "mix"), default="chain")
     ap.add_argument("--n-sites", type=int, default=1024)
     ap.add_argument("--chi", type=int, nargs="+", default=[256])
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
@@ -262,10 +309,14 @@ def main(argv=None):
     ap.add_argument("--min-gain", type=float, default=0.01)
     ap.add_argument("--seed", type=int, default=0)
     a = ap.parse_args(argv)
-    for chi in a.chi:
-        e = tune(a.n_sites, chi, a.precision, a.cache, a.seed, a.timed_layers, a.repeats,
-                 a.passes, log=lambda s: print(s, flush=True), min_gain=a.min_gain)
-        print(json.dumps({"chi": chi, "best": e["params"], "ms": e["ms"],
+    if a.workload == "chain":
+        specs = [chain_spec(a.n_sites, chi, a.seed, a.timed_layers) for chi in a.chi]
+    else:
+        specs = [workload_spec(a.workload, a.timed_layers)]
+    for spec in specs:
+        e = tune_spec(spec, a.precision, a.cache, a.repeats, a.passes,
+                      log=lambda s: print(s, flush=True), min_gain=a.min_gain)
+        print(json.dumps({"workload": spec["workload"], "best": e["params"], "ms": e["ms"],
                           "default_ms": e["default_ms"]}), flush=True)
 
 

@@ -1,0 +1,166 @@
+"""The two workload shapes beside the 1D benchmark chain, as seeded inputs, and a timed run of
+each through the C ABI.
+
+* ``lattice``: a 2D random circuit on an 8 x 8 lattice, Haar SU(4) gates on the couplings of
+  the layers A, B, C, D in turn (the lattice layering of App. A), physical depth 12, compiled
+  to the nearest-neighbour layers of the 64-site column path (C and D routed by SWAP layers,
+  ``circuits.compile_2d``: 75 compiled layers, at most 32 gates each), chi_max = 512.
+* ``mix``: 64 independent 1D Haar brickwork circuits, N drawn uniformly from 50..400 and the
+  bond-dimension cap from {64, 128, 256}, depth 16, all states in one handle and one
+  ``apply_layer`` per layer (each gate truncated to its own state's cap).
+
+Both are the inputs of the GPU parity tests of these shapes; ``run`` times a whole circuit on
+the mixed path with the SVD schedule the autotuner cached for the shape, and (optionally)
+reports the fidelity error of every state against the same circuit on the FP64 path.
+
+Command line (one MI355X)::
+
+    python -m paper_2312_02667_amd.workloads --workload lattice
+    python -m paper_2312_02667_amd.workloads --workload mix --no-autotune
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from . import circuits, inputs
+
+LATTICE = dict(lx=8, ly=8, depth=12, seed=404, chi=512)
+MIX = dict(n_circ=64, depth=16, seed=505, circuit_seed=600, n_lo=50, n_hi=400,
+           caps=(64, 128, 256))
+
+
+def lattice_circuit(lx: int = LATTICE["lx"], ly: int = LATTICE["ly"],
+                    depth: int = LATTICE["depth"], seed: int = LATTICE["seed"]) -> list:
+    """Compiled layers (bonds, gates) of the 2D Haar circuit on an lx x ly lattice."""
+    rng = np.random.default_rng(seed)
+    physical = []
+    for layer in range(depth):
+        kind = layer % 4
+        physical.append((kind, {}, [(a, b, inputs.haar_unitary(rng))
+                                    for a, b in circuits.lattice_couplings(lx, ly, kind)]))
+    return circuits.compile_2d(lx, ly, physical)
+
+
+def batched_mix(n_circ: int = MIX["n_circ"], depth: int = MIX["depth"], seed: int = MIX["seed"],
+                circuit_seed: int = MIX["circuit_seed"]):
+    """(ns, caps, circuits): the chain lengths, the caps and each chain's brickwork layers."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(MIX["n_lo"], MIX["n_hi"] + 1, n_circ)
+    caps = rng.choice(list(MIX["caps"]), n_circ)
+    circs = [inputs.brickwork_circuit(int(n), depth, seed=circuit_seed, circuit_id=c)
+             for c, n in enumerate(ns)]
+    return ns, caps, circs
+
+
+def mix_layer(circs: list, layer: int):
+    """Layer ``layer`` (0-based) of every circuit, concatenated: (state_idx, bonds, gates)."""
+    sidx, bonds, gates = [], [], []
+    for c, circ in enumerate(circs):
+        b, g = circ[layer]
+        sidx.append(np.full(len(b), c, np.int32))
+        bonds.append(b)
+        gates.append(g)
+    return np.concatenate(sidx), np.concatenate(bonds), np.concatenate(gates)
+
+
+def layer_calls(workload: str):
+    """(n_sites list, caps list, list of apply_layer keyword sets) of a whole workload."""
+    if workload == "lattice":
+        chi = LATTICE["chi"]
+        calls = [dict(bonds=b, gates=g, chi_max=chi) for b, g in lattice_circuit()]
+        return [LATTICE["lx"] * LATTICE["ly"]], [chi], calls
+    if workload == "mix":
+        ns, caps, circs = batched_mix()
+        calls = []
+        for layer in range(MIX["depth"]):
+            sidx, b, g = mix_layer(circs, layer)
+            calls.append(dict(bonds=b, gates=g, chi_max=0, state_idx=sidx))
+        return [int(x) for x in ns], [int(x) for x in caps], calls
+    raise ValueError(f"unknown workload {workload!r}")
+
+
+def run(workload: str, precision: str = "fp32", cache: str | None = None,
+        eps_reading: str = "complement", fp64_check: bool = True, log=print) -> dict:
+    """Apply a whole workload on the GPU; returns its timing and accuracy record."""
+    from . import autotune, ptebd
+
+    n_sites, caps, calls = layer_calls(workload)
+    m = ptebd.MPS(n_sites, caps, precision)
+    n_gates = max(len(c["bonds"]) for c in calls)
+    key, params = autotune.cache_key(precision, max(caps), n_gates), None
+    if cache:
+        key, params = autotune.apply(m, cache, max(caps), n_gates)
+    schedule = m.svd_params()
+    device_ms, updates, unconverged = 0.0, 0, 0
+    eps_sum = np.zeros(len(n_sites))
+    ptebd.device_synchronize()
+    t0 = time.perf_counter()
+    for kw in calls:
+        st = m.apply_layer(**kw, cutoff=1e-12, eps_reading=eps_reading)
+        device_ms += st["device_ms"]
+        updates += len(kw["bonds"])
+        unconverged += int(st["n_unconverged"])
+        np.add.at(eps_sum, kw.get("state_idx", np.zeros(len(kw["bonds"]), np.int32)), st["eps"])
+    ptebd.device_synchronize()
+    wall = time.perf_counter() - t0
+    rec = {"workload": workload, "precision": precision, "states": len(n_sites),
+           "sites": int(sum(n_sites)), "layers": len(calls), "bond_updates": updates,
+           "device_ms": round(device_ms, 2), "wall_s": round(wall, 3),
+           "bond_updates_per_s": round(updates / wall, 1), "n_unconverged": unconverged,
+           "max_bond": max(max(m.bond_dims(s)) for s in range(len(n_sites))),
+           "eps_sum_median": float(np.median(eps_sum)), "eps_sum_max": float(eps_sum.max()),
+           "eps_reading": eps_reading, "schedule_key": key, "tuned": params is not None,
+           "schedule": {k: schedule[k] for k in autotune.SEARCH_SPACE if k in schedule}}
+    log(f"{workload}: {updates} bond updates in {wall:.2f} s ({device_ms:.0f} ms device)")
+    m.close()
+    if fp64_check and precision != "fp64":
+        # the same circuit again on the mixed path (bit-identical to the timed run) beside
+        # the FP64 path, compared after every layer
+        a = ptebd.MPS(n_sites, caps, precision)
+        a.set_svd_params(**schedule)
+        ref = ptebd.MPS(n_sites, caps, "fp64")
+        per_layer = []
+        for i, kw in enumerate(calls):
+            a.apply_layer(**kw, cutoff=1e-12, eps_reading=eps_reading)
+            ref.apply_layer(**kw, cutoff=1e-12, eps_reading=eps_reading)
+            errs = []
+            for s in range(len(n_sites)):
+                na, nb = a.norm(s), ref.norm(s)
+                errs.append(1.0 - abs(a.overlap(ref, s, s)) ** 2 / (na * na * nb * nb))
+            per_layer.append(float(max(errs)))
+            if i % 10 == 9 or i == len(calls) - 1:
+                log(f"layer {i + 1}: err_F {per_layer[-1]:.3e} (largest over the states)")
+        rec["err_F_per_layer"] = [float(f"{e:.3e}") for e in per_layer]
+        rec["err_F_max_final"] = float(max(errs))
+        rec["err_F_median_final"] = float(np.median(errs))
+        rec["bond_dims_equal"] = all(a.bond_dims(s) == ref.bond_dims(s)
+                                     for s in range(len(n_sites)))
+        a.close()
+        ref.close()
+    return rec
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--workload", choices=("lattice", "mix"), required=True)
+    ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--cache", default=os.path.join(os.path.dirname(__file__),
+                                                    "autotune_cache.json"))
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
+    ap.add_argument("--eps-reading", choices=("literal", "relative", "complement"),
+                    default="complement")
+    ap.add_argument("--no-fp64-check", action="store_true")
+    a = ap.parse_args(argv)
+    rec = run(a.workload, a.precision, None if a.no_autotune else a.cache, a.eps_reading,
+              not a.no_fp64_check, log=lambda s: print(s, flush=True))
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -3,6 +3,7 @@ of known optimum), rejection of candidates that fail the checks, and the JSON ca
 
 import json
 
+import numpy as np
 import pytest
 
 from paper_2312_02667_amd import autotune
@@ -154,3 +155,25 @@ def test_committed_cache_is_valid():
         assert e["ms"] <= e["default_ms"] and e["evaluated"], key
     assert autotune.lookup(cache, "fp32", 256, 512) is not None
     assert autotune.lookup(cache, "fp64", 256, 511) is not None
+
+
+def test_workload_specs_and_their_cache_keys():
+    """The lattice and batched-mix workloads as tuning inputs: set-up and timed layers in
+    order, and the keys their runs look up (largest cap, largest layer's gate bucket)."""
+    from paper_2312_02667_amd import workloads
+
+    for name, first, key in (("lattice", 39, "fp32/theta1024/gates32"),
+                             ("mix", 10, "fp32/theta512/gates8192")):
+        n_sites, caps, calls = workloads.layer_calls(name)
+        spec = autotune.workload_spec(name, 3)
+        assert spec["n_sites"] == n_sites and spec["caps"] == caps
+        assert len(spec["setup"]) == first and len(spec["timed"]) == 3
+        assert np.array_equal(spec["timed"][0]["bonds"], calls[first]["bonds"])
+        n_gates = max(len(c["bonds"]) for c in calls)
+        assert autotune.cache_key("fp32", max(caps), n_gates) == key
+        assert max(len(kw["bonds"]) for kw in spec["timed"]) <= n_gates
+    with pytest.raises(ValueError):
+        autotune.workload_spec("mix", 7)     # 10 set-up + 7 timed > 16 layers
+    chain = autotune.chain_spec(64, 16, seed=1, timed_layers=2)
+    assert len(chain["setup"]) == 5 and len(chain["timed"]) == 2
+    assert all(kw["chi_max"] == 16 for kw in chain["setup"] + chain["timed"])

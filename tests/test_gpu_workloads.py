@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import ptebd_oracle as po
-from paper_2312_02667_amd import circuits, inputs, ptebd
+from paper_2312_02667_amd import ptebd, workloads
 from tests.gpu_util import oracle_cutoff, say
 
 pytestmark = pytest.mark.gpu
@@ -69,15 +69,8 @@ def test_2d_lattice_chi512_sampled_parity():
     norm grows with every saturated layer of this circuit until a discarded weight reaches 1).
     At each of the last three compiled layers, the largest bond update is recomputed by the
     oracle from the GPU's state before the layer."""
-    lx = ly = 8
-    rng = np.random.default_rng(404)
-    physical = []
-    for layer in range(12):
-        kind = layer % 4
-        physical.append((kind, {}, [(a, b, inputs.haar_unitary(rng))
-                                    for a, b in circuits.lattice_couplings(lx, ly, kind)]))
-    layers = circuits.compile_2d(lx, ly, physical)
-    n, chi = lx * ly, 512
+    layers = workloads.lattice_circuit()
+    n, chi = 64, 512
     m = ptebd.MPS(n, chi, "fp32")
     checked = 0
     for li, (bonds, gates) in enumerate(layers):
@@ -107,24 +100,15 @@ def test_batched_mix_of_circuits_sampled_parity():
     with chi_max = 0 (each gate truncated to its own state's cap).  Four circuits are also
     run alone and must agree bit for bit; in the last layer two bonds of four circuits are
     recomputed by the oracle."""
-    rng = np.random.default_rng(505)
     n_circ, depth = 64, 16
-    ns = rng.integers(50, 401, n_circ)
-    caps = rng.choice([64, 128, 256], n_circ)
-    circs = [inputs.brickwork_circuit(int(n), depth, seed=600, circuit_id=c) for c, n in enumerate(ns)]
+    ns, caps, circs = workloads.batched_mix(n_circ, depth)
     say(f"batched mix: {n_circ} circuits, {int(ns.sum())} sites, caps {np.bincount(caps)[[64, 128, 256]]}")
     batched = ptebd.MPS([int(x) for x in ns], [int(x) for x in caps], "fp32")
     alone_ids = [int(np.argmax(caps == 256)), int(np.argmax(caps == 64)), 5, 17]
     alone = {c: ptebd.MPS(int(ns[c]), int(caps[c]), "fp32") for c in alone_ids}
     check_ids = alone_ids
     for layer in range(depth):
-        sidx, bonds, gates = [], [], []
-        for c, circ in enumerate(circs):
-            b, g = circ[layer]
-            sidx.append(np.full(len(b), c, np.int32))
-            bonds.append(b)
-            gates.append(g)
-        sidx, bonds, gates = np.concatenate(sidx), np.concatenate(bonds), np.concatenate(gates)
+        sidx, bonds, gates = workloads.mix_layer(circs, layer)
         last = layer == depth - 1
         befores = {}
         if last:
