@@ -147,6 +147,22 @@ __device__ inline void load4(bool ok, gptr<const cplx<T>> p, cplx<T> (&o)[4]) {
   }
 }
 
+// XCD-aware work order for per-gate tiles, on a one-dimensional grid of `per_gate` slots per
+// gate for the gate count rounded up to a multiple of 8 (xcd_grid).  The workgroups of a
+// launch are handed to the eight XCDs in turn (workgroup L to XCD L % 8), so giving slot L to
+// gate 8 (L / 8 / per_gate) + L % 8 keeps every tile of a gate on one XCD: the operand panels
+// its tiles share are read into that XCD's L2 once instead of once per XCD.  A gate index at
+// or past the gate count is padding, to be skipped by the caller.
+__device__ inline void xcd_gate_tile(int per_gate, int& gate, int& tile) {
+  const int slot = (int)(blockIdx.x >> 3);
+  gate = (slot / per_gate) * 8 + (int)(blockIdx.x & 7);
+  tile = slot % per_gate;
+}
+
+inline unsigned xcd_grid(int per_gate, int n_gates) {
+  return (unsigned)per_gate * (unsigned)((n_gates + 7) / 8 * 8);
+}
+
 // Round-robin (circle method) tournament: player in `slot` during `round`, for an even
 // number of players; slot 0 is fixed, the others rotate.  Pairs are (p, nplayers-1-p).
 __device__ inline int rr_player(int slot, int round, int nplayers) {

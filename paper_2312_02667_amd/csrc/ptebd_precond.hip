@@ -101,14 +101,16 @@ __device__ inline void tile_of(int t, int nt, int& ti, int& tj) {
 }
 
 __global__ __launch_bounds__(256) void gram64_kernel(const GateDesc* __restrict__ descs,
-                                                     PrecondOut po) {
-  const int g = blockIdx.y;
+                                                     int n_gates, int per_gate, PrecondOut po) {
+  int g, tile;
+  xcd_gate_tile(per_gate, g, tile);  // a gate's tiles on one XCD, its columns in one L2
+  if (g >= n_gates) return;
   const GateDesc* d = descs + g;
   const int R = d->R, C = d->C;
   const int nt = (C + 31) >> 5;
-  if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+  if (tile >= nt * (nt + 1) / 2) return;
   int ti, tj;
-  tile_of(blockIdx.x, nt, ti, tj);
+  tile_of(tile, nt, ti, tj);
   const gptr<const z32> __restrict__ W = as_global((const z32*)d->w);
   const int* __restrict__ ps = po.ps + (size_t)g * po.cmax;
   z64* __restrict__ G = (z64*)d->gram;
@@ -327,27 +329,29 @@ __global__ __launch_bounds__(256) void trsm_kernel(const GateDesc* __restrict__ 
 
 // Deferred updates of the blocked Cholesky: G[ti, tj] -= sum_l R[l, ti]^H R[l, tj] over the
 // rows l in [32 l0, 32 l1) of R, which the earlier panels left in the upper triangle of G.
-// mode 0: the block row ti = kb, tiles tj = kb + blockIdx.x, before panel kb is factored
+// mode 0: the block row ti = kb, tiles tj = kb + tile, before panel kb is factored
 // (the rows of the panels since the last trailing update); mode 1: the upper tiles
 // kb < ti <= tj once panel kb has closed a group (a rank 32 (l1 - l0) trailing update).
 // Every operand entry has l < ti * 32 <= column, so it lies in the strict upper triangle,
 // and no tile written here is read by the same launch.  Four waves, each a 16 x 16
 // sub-tile on FP64 MFMA; K in steps of 16 rows with the next step's loads in flight,
 // operands straight from global memory (column-major G: a column's rows are contiguous).
-__global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ descs, int kb,
-                                                   int l0, int l1, int mode) {
-  const int g = blockIdx.y;
+__global__ __launch_bounds__(256) void herk_kernel(const GateDesc* __restrict__ descs, int n_gates,
+                                                   int per_gate, int kb, int l0, int l1, int mode) {
+  int g, tile;
+  xcd_gate_tile(per_gate, g, tile);  // a gate's tiles on one XCD, its R rows in one L2
+  if (g >= n_gates) return;
   const int C = descs[g].C;
   const int nt = (C + 31) >> 5;
   int ti, tj;
   if (mode == 0) {
     ti = kb;
-    tj = kb + (int)blockIdx.x;
+    tj = kb + tile;
     if (tj >= nt) return;
   } else {
     const int nrem = nt - kb - 1;
-    if (nrem <= 0 || (int)blockIdx.x >= nrem * (nrem + 1) / 2) return;
-    tile_of(blockIdx.x, nrem, ti, tj);
+    if (nrem <= 0 || tile >= nrem * (nrem + 1) / 2) return;
+    tile_of(tile, nrem, ti, tj);
     ti += kb + 1;
     tj += kb + 1;
   }
@@ -489,14 +493,16 @@ __global__ void yhat_kernel(const GateDesc* __restrict__ jdescs, PrecondOut po, 
 // P1 = x u, P2 = y v, P3 = (x + y)(u + v); Re ab = P1 - P2, Im ab = P3 - P1 - P2.  Written
 // into the column c of the U buffer (R x C), unnormalized (the write-back divides by sigma).
 __global__ __launch_bounds__(256) void ugemm_kernel(const GateDesc* __restrict__ descs,
-                                                    LayerOut out) {
-  const int g = blockIdx.y;
+                                                    int n_gates, int per_gate, LayerOut out) {
+  int g, tile;
+  xcd_gate_tile(per_gate, g, tile);  // a gate's tiles on one XCD, its W and Y in one L2
+  if (g >= n_gates) return;
   const GateDesc* d = descs + g;
   const int R = d->R, C = d->C;
   const int k = out.k[g];
   const int tr = (R + 31) >> 5, tk = (k + 31) >> 5;
-  if ((int)blockIdx.x >= tr * tk) return;
-  const int r0 = (blockIdx.x % tr) * 32, j0 = (blockIdx.x / tr) * 32;
+  if (tile >= tr * tk) return;
+  const int r0 = (tile % tr) * 32, j0 = (tile / tr) * 32;
   const z32* __restrict__ W = (const z32*)d->w;
   const z32* __restrict__ Y = (const z32*)d->gram;
   z32* __restrict__ U = (z32*)d->left;
@@ -565,9 +571,9 @@ void launch_colsort(const GateDesc* d_desc, int n_gates, const PrecondOut& po,
 
 void launch_gram64(const GateDesc* d_desc, int n_gates, int max_c, const PrecondOut& po,
                    hipStream_t stream) {
-  const int nt = (max_c + 31) / 32;
-  hipLaunchKernelGGL(gram64_kernel, dim3(nt * (nt + 1) / 2, n_gates), dim3(256), 0, stream,
-                     d_desc, po);
+  const int nt = (max_c + 31) / 32, per_gate = nt * (nt + 1) / 2;
+  hipLaunchKernelGGL(gram64_kernel, dim3(xcd_grid(per_gate, n_gates)), dim3(256), 0, stream,
+                     d_desc, n_gates, per_gate, po);
 }
 
 // Panels of 32 columns; the trailing matrix is updated once per group of kGroup panels (a
@@ -581,15 +587,15 @@ void launch_cholesky(const GateDesc* d_desc, int n_gates, int max_c, const Preco
   for (int kb = 0; kb < nt; ++kb) {
     const int kb0 = kb - kb % kGroup;
     if (kb > kb0)
-      hipLaunchKernelGGL(herk_kernel, dim3(nt - kb, n_gates), dim3(256), 0, stream, d_desc, kb,
-                         kb0, kb, 0);
+      hipLaunchKernelGGL(herk_kernel, dim3(xcd_grid(nt - kb, n_gates)), dim3(256), 0, stream,
+                         d_desc, n_gates, nt - kb, kb, kb0, kb, 0);
     hipLaunchKernelGGL(potrf_kernel, dim3(n_gates), dim3(256), 0, stream, d_desc, po, kb);
     const int nrem = nt - kb - 1;
     if (nrem <= 0) break;
     hipLaunchKernelGGL(trsm_kernel, dim3(nrem, n_gates), dim3(256), 0, stream, d_desc, kb);
     if (kb % kGroup == kGroup - 1)
-      hipLaunchKernelGGL(herk_kernel, dim3(nrem * (nrem + 1) / 2, n_gates), dim3(256), 0, stream,
-                         d_desc, kb, kb0, kb + 1, 1);
+      hipLaunchKernelGGL(herk_kernel, dim3(xcd_grid(nrem * (nrem + 1) / 2, n_gates)), dim3(256),
+                         0, stream, d_desc, n_gates, nrem * (nrem + 1) / 2, kb, kb0, kb + 1, 1);
   }
 }
 
@@ -604,7 +610,8 @@ void launch_recover(const GateDesc* d_desc, const GateDesc* d_jdesc, int n_gates
   const int blocks = std::max(1, std::min(256, (max_c * max_c + 255) / 256));
   hipLaunchKernelGGL(yhat_kernel, dim3(blocks, n_gates), dim3(256), 0, stream, d_jdesc, po, out);
   const int tiles = ((max_r + 31) / 32) * ((max_c + 31) / 32);
-  hipLaunchKernelGGL(ugemm_kernel, dim3(tiles, n_gates), dim3(256), 0, stream, d_desc, out);
+  hipLaunchKernelGGL(ugemm_kernel, dim3(xcd_grid(tiles, n_gates)), dim3(256), 0, stream, d_desc,
+                     n_gates, tiles, out);
 }
 
 }  // namespace ptebd

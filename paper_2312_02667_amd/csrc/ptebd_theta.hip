@@ -14,15 +14,20 @@ namespace {
 // sub-tile of all four products; K (= chi_{q+1}) staged through LDS in steps of 16, the next
 // step's entries loaded into registers while the current step's products run.  Built
 // for four waves per SIMD in FP32 (the three-product form's third accumulators fit without
-// spills) and two in FP64.
+// spills) and two in FP64.  Tiles in the XCD-aware order of xcd_gate_tile: every tile of a
+// gate on one XCD, which reads the gate's Gamma panels into its L2 once.
 template <class T>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void theta_kernel(const GateDesc* __restrict__ descs) {
-  const GateDesc* d = descs + blockIdx.y;
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void theta_kernel(const GateDesc* __restrict__ descs,
+                                                                            int n_gates, int max_tiles) {
+  int gate, tile;
+  xcd_gate_tile(max_tiles, gate, tile);
+  if (gate >= n_gates) return;
+  const GateDesc* d = descs + gate;
   const int cl = d->cl, cm = d->cm, cr = d->cr;
   const int tiles_c = (cr + 31) >> 5;
   const int tiles = ((cl + 31) >> 5) * tiles_c;
-  if ((int)blockIdx.x >= tiles) return;
-  const int a0 = (blockIdx.x / tiles_c) * 32, c0 = (blockIdx.x % tiles_c) * 32;
+  if (tile >= tiles) return;
+  const int a0 = (tile / tiles_c) * 32, c0 = (tile % tiles_c) * 32;
 
   __shared__ cplx<T> As[2][16][33];
   __shared__ cplx<T> Bs[2][16][33];
@@ -185,7 +190,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) void theta_kernel(cons
 template <class T>
 void launch_theta(const GateDesc* d_desc, int n_gates, int max_tiles, hipStream_t stream) {
   if (n_gates <= 0 || max_tiles <= 0) return;
-  hipLaunchKernelGGL(theta_kernel<T>, dim3(max_tiles, n_gates), dim3(256), 0, stream, d_desc);
+  hipLaunchKernelGGL(theta_kernel<T>, dim3(xcd_grid(max_tiles, n_gates)), dim3(256), 0, stream,
+                     d_desc, n_gates, max_tiles);
 }
 
 template void launch_theta<float>(const GateDesc*, int, int, hipStream_t);

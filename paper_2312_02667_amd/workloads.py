@@ -30,6 +30,7 @@ import numpy as np
 
 from . import circuits, inputs
 
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 LATTICE = dict(lx=8, ly=8, depth=12, seed=404, chi=512)
 MIX = dict(n_circ=64, depth=16, seed=505, circuit_seed=600, n_lo=50, n_hi=400,
            caps=(64, 128, 256))
@@ -85,9 +86,10 @@ def layer_calls(workload: str):
     raise ValueError(f"unknown workload {workload!r}")
 
 
-def run(workload: str, precision: str = "fp32", cache: str | None = None,
+def run(workload: str, precision: str = "fp32", cache: str | None = CACHE,
         eps_reading: str = "complement", fp64_check: bool = True, log=print) -> dict:
-    """Apply a whole workload on the GPU; returns its timing and accuracy record."""
+    """Apply a whole workload on the GPU with the SVD schedule ``cache`` holds for its shape
+    (None: the default schedule); returns its timing and accuracy record."""
     from . import autotune, ptebd
 
     n_sites, caps, calls = layer_calls(workload)
@@ -150,8 +152,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--workload", choices=("lattice", "mix"), required=True)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
-    ap.add_argument("--cache", default=os.path.join(os.path.dirname(__file__),
-                                                    "autotune_cache.json"))
+    ap.add_argument("--cache", default=CACHE)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
     ap.add_argument("--eps-reading", choices=("literal", "relative", "complement"),
                     default="complement")
